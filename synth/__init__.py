@@ -1,0 +1,119 @@
+"""Seeded synthetic inputs for the RLWE-PIR first-dimension scan.
+
+This module is the only code shared by the CPU oracle and the GPU path.
+It draws random numbers and nothing else: it holds none of the scheme's
+arithmetic (no NTT, no modular products, no encryption).  Every value the
+scheme would draw at random -- the database bytes, the ternary secret, the
+uniform mask polynomials, the Gaussian errors, the queried indices -- is
+produced here from a seed and handed to whichever side consumes it.
+
+Streams.  Each object comes from its own PCG64 generator seeded through a
+SeedSequence whose entropy is ``[seed, TAG, index...]``, so any row of the
+database or any query can be regenerated on its own, in any order, without
+drawing the others:
+
+* database row ``i``          -> ``[seed, TAG_DB, i]``: ``C*N`` uint8, ``[C][N]``;
+* secret of query ``b``       -> ``[seed, TAG_SECRET, b]``: ``N`` values in {-1,0,1};
+* mask row ``i`` of query ``b`` -> ``[seed, TAG_MASK, b, i]``: one ``N``-vector
+  uniform in ``[0, q_k)`` per prime, primes in the order given;
+* error row ``i`` of query ``b`` -> ``[seed, TAG_ERROR, b, i]``: ``N`` rounded
+  normals of standard deviation ``sigma``, resampled while ``|e| > clip``;
+* queried indices             -> ``[seed, TAG_INDEX]``: ``B`` integers in ``[0, R)``;
+* uniform ciphertext stand-ins -> ``[seed, TAG_UNIFORM, b, i]``: used where a
+  workload needs ciphertext-shaped data without a key (an RLWE ciphertext is
+  indistinguishable from uniform, so the scan sees the same distribution).
+
+The error clip ``|e| <= 19`` is the fresh-noise bound ``|e| < 6*sigma`` with
+``sigma = 3.2`` (cryptographic background, LWE paragraph), applied to RLWE too.
+"""
+
+from __future__ import annotations
+
+import numpy as np
+
+TAG_DB = 0xDB
+TAG_SECRET = 0x5EC
+TAG_MASK = 0xA0
+TAG_ERROR = 0xE0
+TAG_INDEX = 0x1D
+TAG_UNIFORM = 0xBE
+TAG_SIZES = 0x51
+TAG_FREIVALDS = 0xF5
+
+SIGMA = 3.2
+ERROR_CLIP = 19
+
+
+def _rng(*entropy: int) -> np.random.Generator:
+    return np.random.Generator(np.random.PCG64(np.random.SeedSequence(list(entropy))))
+
+
+def db_row(seed: int, i: int, C: int, N: int) -> np.ndarray:
+    """Row ``i`` of the plaintext database: ``[C][N]`` uint8 coefficients."""
+    return _rng(seed, TAG_DB, i).integers(0, 256, size=(C, N), dtype=np.uint8)
+
+
+def db_bytes(seed: int, R: int, C: int, N: int, rows: range | None = None) -> np.ndarray:
+    """The database ``[R][C][N]`` uint8, or the listed rows of it."""
+    rows = range(R) if rows is None else rows
+    out = np.empty((len(rows), C, N), dtype=np.uint8)
+    for r, i in enumerate(rows):
+        out[r] = db_row(seed, i, C, N)
+    return out
+
+
+def db_bytes_into(seed: int, out: np.ndarray, row0: int = 0) -> None:
+    """Fill ``out`` (``[rows][C][N]`` uint8) with database rows starting at ``row0``."""
+    _, C, N = out.shape
+    for r in range(out.shape[0]):
+        out[r] = db_row(seed, row0 + r, C, N)
+
+
+def secret(seed: int, b: int, N: int) -> np.ndarray:
+    """Ternary secret of query ``b``: int64 values in {-1, 0, 1}."""
+    return _rng(seed, TAG_SECRET, b).integers(-1, 2, size=N, dtype=np.int64)
+
+
+def mask_row(seed: int, b: int, i: int, primes: list[int], N: int) -> np.ndarray:
+    """Uniform mask ``a`` of ciphertext ``i`` of query ``b``: ``[K][N]`` uint64 in ``[0, q_k)``."""
+    g = _rng(seed, TAG_MASK, b, i)
+    return np.stack([g.integers(0, q, size=N, dtype=np.uint64) for q in primes])
+
+
+def error_row(seed: int, b: int, i: int, N: int, sigma: float = SIGMA,
+              clip: int = ERROR_CLIP) -> np.ndarray:
+    """Rounded-Gaussian error of ciphertext ``i`` of query ``b``: ``N`` int64, ``|e| <= clip``."""
+    g = _rng(seed, TAG_ERROR, b, i)
+    e = np.rint(g.normal(0.0, sigma, size=N)).astype(np.int64)
+    bad = np.abs(e) > clip
+    while bad.any():
+        e[bad] = np.rint(g.normal(0.0, sigma, size=int(bad.sum()))).astype(np.int64)
+        bad = np.abs(e) > clip
+    return e
+
+
+def indices(seed: int, B: int, R: int) -> np.ndarray:
+    """Queried row of each of ``B`` queries: int64 in ``[0, R)``."""
+    return _rng(seed, TAG_INDEX).integers(0, R, size=B, dtype=np.int64)
+
+
+def uniform_query(seed: int, b: int, R: int, primes: list[int], N: int) -> np.ndarray:
+    """Ciphertext-shaped uniform data for query ``b``: ``[R][2][K][N]`` uint32, entry < q_k."""
+    K = len(primes)
+    out = np.empty((R, 2, K, N), dtype=np.uint32)
+    for i in range(R):
+        g = _rng(seed, TAG_UNIFORM, b, i)
+        for c in range(2):
+            for k, q in enumerate(primes):
+                out[i, c, k] = g.integers(0, q, size=N, dtype=np.uint32)
+    return out
+
+
+def batch_sizes(seed: int, n_db: int, lo: int = 1, hi: int = 64) -> np.ndarray:
+    """Per-database query counts for a multi-database batch: int64 in ``[lo, hi]``."""
+    return _rng(seed, TAG_SIZES).integers(lo, hi + 1, size=n_db, dtype=np.int64)
+
+
+def freivalds_vector(seed: int, draw: int, C: int, q: int) -> np.ndarray:
+    """Random weights for a Freivalds check: ``C`` uint64 uniform in ``[0, q)``."""
+    return _rng(seed, TAG_FREIVALDS, draw, q).integers(0, q, size=C, dtype=np.uint64)
