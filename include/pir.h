@@ -1,0 +1,201 @@
+/*
+ * pir.h -- C ABI of libpir, the GPU hot path of single-server RLWE PIR:
+ * the first-dimension database scan of poly-HE folding and the negacyclic
+ * NTT/INTT that feed and drain it, for AMD Instinct MI355X (gfx950).
+ *
+ * What is computed (paper: Sec. 3.2, poly-HE folding steps 5 and 6; Sec. 4,
+ * "INT32 modular GEMM"; Sec. 2.3, RNS and NTT).  The server holds a database
+ * of R x C plaintext polynomials DB[i][j] in R_p = Z_p[X]/(X^N+1).  A query is
+ * R RLWE ciphertexts ct_i = (a_i, b_i) in R_Q^2, Q = q_0 * ... * q_{K-1}.  The
+ * answer is, for every column j,
+ *
+ *      answer_j = sum_i DB[i][j] * ct_i        in R_Q^2,
+ *
+ * computed per RNS prime q_k in NTT form, where it becomes, for every slot t,
+ * an exact modular matrix product Y_t = D_t^T * Q_t (mod q_k) of shape
+ * (C x R) * (R x 2B) for a batch of B queries.
+ *
+ * Conventions shared by every call.
+ *  - Residues are uint32 in [0, q_k).  A polynomial is stored as K rows of N
+ *    residues, one row per prime ("[K][N]", RNS matrix of Sec. 2.3).
+ *  - NTT form: slot t of the transform of a(X) mod q_k holds
+ *    a(psi_k^(2*brv(t)+1)) mod q_k, brv = bit reversal over log2(N) bits, and
+ *    psi_k = the smallest integer x >= 2 with x^N = -1 (mod q_k).  The inverse
+ *    transform includes the factor N^-1.
+ *  - A ciphertext is [2][K][N]: component 0 = a, component 1 = b (App. A.2).
+ *  - Query layout [B][R][2][K][N]; answer layout [B][C][2][K][N].
+ *  - The database lift maps a byte v to the residue v (unsigned lift).
+ *  - Pointers documented "device" must point to device memory of the context's
+ *    GPU; "host" to host memory.  The caller owns every buffer it passes.
+ *  - Every call that takes a stream is asynchronous on that stream (a
+ *    hipStream_t passed as void*; NULL = the null stream).  Buffers must stay
+ *    valid until the stream has passed the work.
+ *  - Errors: every call returns a pir_status.  On error nothing useful is
+ *    guaranteed in the outputs; pir_last_error(ctx) describes the failure.
+ *    No C++ exception crosses this boundary.
+ *  - A context is not thread-safe: use one context per host thread.
+ */
+#ifndef PIR_H_
+#define PIR_H_
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define PIR_MAX_PRIMES 4
+#define PIR_MIN_LOG2_N 10
+#define PIR_MAX_LOG2_N 12
+#define PIR_PRIME_BITS 28 /* every q_k < 2^28 */
+#define PIR_MAX_R 32768u  /* rows: bounds the exact int32 limb sums */
+#define PIR_MAX_C 65536u
+
+typedef enum {
+  PIR_OK = 0,
+  PIR_ERR_INVALID_ARG = 1,   /* null pointer, size out of range, bad layout */
+  PIR_ERR_UNSUPPORTED = 2,   /* parameters outside what the kernels handle */
+  PIR_ERR_OUT_OF_MEMORY = 3, /* a device or host allocation failed */
+  PIR_ERR_BUDGET = 4,        /* the context's HBM budget would be exceeded */
+  PIR_ERR_DEVICE = 5,        /* a HIP runtime call failed */
+  PIR_ERR_NOT_READY = 6      /* asked for a result that is not available yet */
+} pir_status;
+
+typedef void *pir_stream; /* hipStream_t */
+
+typedef struct pir_ctx pir_ctx; /* one per device: tables, workspace, budget */
+typedef struct pir_db pir_db;   /* device-resident NTT-form database */
+
+/* RNS parameters (Sec. 2.3; prime rule of App. A, "RNS prime selection").
+ * N = 2^log2_n with 10 <= log2_n <= 12; 1 <= n_primes <= 4; each primes[k]
+ * prime, < 2^28, = 1 (mod 2N), all distinct; p = 2^plain_log2 with
+ * 1 <= plain_log2 <= 8 (database bytes are plaintext coefficients). */
+typedef struct {
+  uint32_t log2_n;
+  uint32_t n_primes;
+  uint32_t primes[PIR_MAX_PRIMES];
+  uint32_t plain_log2;
+} pir_params;
+
+/* Human-readable name of a status code (static storage). */
+const char *pir_status_string(pir_status s);
+
+/* Library version string (static storage). */
+const char *pir_version(void);
+
+/* The `count` largest primes q < 2^bound_log2 with q = 1 (mod 2^(log2_n+1)),
+ * in descending order (App. A, RNS prime selection).  Host only; `out` is a
+ * host array of `count` entries.  INVALID_ARG if log2_n > 20, bound_log2 > 31,
+ * count == 0 or too few primes exist. */
+pir_status pir_find_primes(uint32_t log2_n, uint32_t count, uint32_t bound_log2,
+                           uint32_t *out);
+
+/* Validate `params`; on success write psi_k (the NTT root, see above) for each
+ * prime into `psi_out` (host, n_primes entries; may be NULL).  Host only. */
+pir_status pir_params_check(const pir_params *params, uint32_t *psi_out);
+
+/* Create a context on HIP device `device`.  `hbm_budget_bytes` caps the device
+ * memory the context may hold (databases + workspace); 0 = no cap beyond the
+ * device.  *out receives the context; release it with pir_ctx_destroy. */
+pir_status pir_ctx_create(int device, size_t hbm_budget_bytes, pir_ctx **out);
+
+/* Release the context (after freeing its databases).  Waits for the device. */
+void pir_ctx_destroy(pir_ctx *ctx);
+
+/* Text of the last error on `ctx` (valid until the next call on it). */
+const char *pir_last_error(const pir_ctx *ctx);
+
+/* Device bytes the context holds right now (databases + workspace). */
+size_t pir_ctx_device_bytes(const pir_ctx *ctx);
+
+/* Make the context's workspace at least `bytes` large now, so that later
+ * calls of that size allocate nothing.  Synchronizes the device when it grows. */
+pir_status pir_ctx_reserve(pir_ctx *ctx, size_t bytes);
+
+/* ---- a1: offline database transform (Sec. 2.4 plaintext bloating; Sec. 3.2
+ * step 5; Sec. 4.2 layout transposition; Sec. 4.3 fused RNS decomposition).
+ * Lifts every byte of `raw` ([R][C][N] uint8, row-major: row i, column j,
+ * coefficient n) into Z_{q_k} for every prime, applies the forward NTT, and
+ * stores the result in the library's scan layout (slot-major, limb-planar
+ * tiles; opaque).  `raw` is device memory if raw_is_device != 0, else host
+ * memory (copied in slabs through pinned staging).  1 <= R <= PIR_MAX_R,
+ * 1 <= C <= PIR_MAX_C.  The database holds R_pad*C_pad*N*K*4 bytes of device
+ * memory (R_pad = R rounded up to 32, C_pad = C rounded up to 8); BUDGET if
+ * that exceeds the context's budget.  The call returns after `raw` has been
+ * consumed (it synchronizes `stream`), so the caller may free `raw` at once.
+ * *out receives the database; release it with pir_db_free. */
+pir_status pir_db_load_ntt(pir_ctx *ctx, const pir_params *params, const uint8_t *raw,
+                           int raw_is_device, uint32_t R, uint32_t C, pir_stream stream,
+                           pir_db **out);
+
+/* Shape and size of a loaded database (any output pointer may be NULL). */
+pir_status pir_db_info(const pir_db *db, pir_params *params, uint32_t *R, uint32_t *C,
+                       size_t *device_bytes);
+
+/* Read back NTT-form database polynomials in canonical layout: rows
+ * [i0, i0+ni) x columns [j0, j0+nj) into `out` (device, [ni][nj][K][N] uint32).
+ * For checking a1 against an independent transform. */
+pir_status pir_db_read_ntt(pir_ctx *ctx, const pir_db *db, uint32_t i0, uint32_t ni,
+                           uint32_t j0, uint32_t nj, uint32_t *out, pir_stream stream);
+
+/* Release a database's device memory (waits for the device). */
+void pir_db_free(pir_db *db);
+
+/* ---- a2/a4: forward / inverse negacyclic NTT (Sec. 2.3; Sec. 4.3),
+ * in place on `polys` (device, [n_polys][K][N] uint32, residues < q_k).
+ * The inverse includes N^-1.  Values >= q_k give unspecified results (never an
+ * out-of-bounds access). */
+pir_status pir_ntt(pir_ctx *ctx, const pir_params *params, uint32_t *polys, size_t n_polys,
+                   pir_stream stream);
+pir_status pir_intt(pir_ctx *ctx, const pir_params *params, uint32_t *polys, size_t n_polys,
+                    pir_stream stream);
+
+/* ---- a3: the scan in NTT form (Sec. 3.2 step 6; Sec. 4 INT32 modular GEMM).
+ * query_ntt: device [B][R][2][K][N], NTT form; answer_ntt: device
+ * [B][C][2][K][N], NTT form, fully overwritten:
+ *   answer[b][j][c][k][t] = sum_i D_k[i][j][t] * query[b][i][c][k][t] (mod q_k).
+ * 1 <= B <= PIR_MAX_BATCH.  Uses context workspace of about
+ * B*R_pad*2*K*N bytes (grown on demand). */
+#define PIR_MAX_BATCH 256u
+pir_status pir_db_mul(pir_ctx *ctx, const pir_db *db, const uint32_t *query_ntt, uint32_t B,
+                      uint32_t *answer_ntt, pir_stream stream);
+
+/* ---- a5: fused batch over several databases (Sec. 2.5 multi-client
+ * batching; Sec. 4.4 stream-wise buffering).  For every job: forward NTT of
+ * its queries, the scan, inverse NTT of its answers -- coefficient form in and
+ * out.  Jobs may name different databases (different N, R, C); the scans of
+ * all jobs run in one launch.  query_coeff: device [B][R][2][K][N] (left
+ * unchanged); answer_coeff: device [B][C][2][K][N]. */
+typedef struct {
+  const pir_db *db;
+  uint32_t B;
+  const uint32_t *query_coeff;
+  uint32_t *answer_coeff;
+} pir_job;
+
+pir_status pir_answer_batch(pir_ctx *ctx, const pir_job *jobs, size_t n_jobs,
+                            pir_stream stream);
+
+/* ---- measurement: per-stage kernel time with HIP events (off by default).
+ * While enabled, pir_db_mul and pir_answer_batch bracket each stage's launch
+ * with a pair of HIP events on the call's stream.  pir_profile_read waits for
+ * the recorded events and returns the summed elapsed time (ms) and the number
+ * of launches of `stage` since profiling was (re-)enabled.  Enabling resets
+ * the sums. */
+typedef enum {
+  PIR_STAGE_NTT = 0,  /* forward NTT of queries */
+  PIR_STAGE_PACK = 1, /* query transposition into scan tiles */
+  PIR_STAGE_SCAN = 2, /* the database scan */
+  PIR_STAGE_INTT = 3, /* inverse NTT of answers */
+  PIR_N_STAGES = 4
+} pir_stage;
+
+pir_status pir_profile_enable(pir_ctx *ctx, int enable);
+pir_status pir_profile_read(pir_ctx *ctx, uint32_t stage, double *total_ms, uint64_t *launches);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* PIR_H_ */

@@ -1,0 +1,615 @@
+// Host side of libpir: the C ABI declared in include/pir.h.
+//
+// Parameter arithmetic (prime search, roots of unity, twiddle and limb-weight
+// tables) is done here on the host in exact 64-bit integer arithmetic; all
+// per-element work runs in the HIP kernels.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <map>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "pir_internal.h"
+
+using namespace pir;
+
+struct pir_ctx {
+  int device = 0;
+  int num_cus = 0;
+  size_t budget = 0;  // 0 = unlimited
+  size_t held = 0;    // device bytes held (databases + workspace + tables)
+  std::string err;
+  void *ws = nullptr;
+  size_t ws_bytes = 0;
+  std::map<std::pair<uint32_t, uint32_t>, uint32_t *> tw_tables;  // (log2n, q) -> [4][N]
+  std::map<std::vector<uint32_t>, DevPrime *> prime_sets;         // (log2n, q...) -> [K]
+  // stage profiling
+  bool prof = false;
+  struct Rec {
+    uint32_t stage;
+    hipEvent_t a, b;
+  };
+  std::vector<Rec> pending;
+  double stage_ms[PIR_N_STAGES] = {};
+  uint64_t stage_n[PIR_N_STAGES] = {};
+};
+
+struct pir_db {
+  pir_ctx *ctx = nullptr;
+  pir_params params{};
+  uint32_t R = 0, C = 0;
+  size_t bytes = 0;
+  uint8_t *atoms = nullptr;
+  DbDesc desc{};
+};
+
+namespace {
+
+// ---------------------------------------------------------------- errors --
+pir_status fail(pir_ctx *ctx, pir_status s, const char *fmt, ...) {
+  if (ctx) {
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    ctx->err = buf;
+  }
+  return s;
+}
+
+#define HIP_OR_FAIL(ctx, expr)                                                           \
+  do {                                                                                   \
+    hipError_t e_ = (expr);                                                              \
+    if (e_ != hipSuccess)                                                                \
+      return fail((ctx), PIR_ERR_DEVICE, "%s failed: %s", #expr, hipGetErrorString(e_)); \
+  } while (0)
+
+struct DeviceGuard {
+  int prev = -1;
+  explicit DeviceGuard(int dev) {
+    if (hipGetDevice(&prev) != hipSuccess) prev = -1;
+    if (prev != dev) (void)hipSetDevice(dev);
+  }
+  ~DeviceGuard() {
+    int cur = -1;
+    if (prev >= 0 && hipGetDevice(&cur) == hipSuccess && cur != prev) (void)hipSetDevice(prev);
+  }
+};
+
+// ------------------------------------------------------- number theory ----
+uint64_t mulmod(uint64_t a, uint64_t b, uint64_t m) {
+  return (uint64_t)((unsigned __int128)a * b % m);
+}
+uint64_t powmod(uint64_t b, uint64_t e, uint64_t m) {
+  uint64_t r = 1 % m;
+  b %= m;
+  while (e) {
+    if (e & 1) r = mulmod(r, b, m);
+    b = mulmod(b, b, m);
+    e >>= 1;
+  }
+  return r;
+}
+// Deterministic Miller-Rabin for n < 2^32 (bases 2, 3, 5, 7 suffice below 3.2e9;
+// 11 and 13 added for margin).
+bool is_prime_u32(uint64_t n) {
+  if (n < 2) return false;
+  static const uint64_t bases[] = {2, 3, 5, 7, 11, 13};
+  for (uint64_t p : bases)
+    if (n % p == 0) return n == p;
+  uint64_t d = n - 1;
+  int r = 0;
+  while ((d & 1) == 0) d >>= 1, ++r;
+  for (uint64_t a : bases) {
+    uint64_t x = powmod(a, d, n);
+    if (x == 1 || x == n - 1) continue;
+    bool comp = true;
+    for (int i = 1; i < r; ++i) {
+      x = mulmod(x, x, n);
+      if (x == n - 1) {
+        comp = false;
+        break;
+      }
+    }
+    if (comp) return false;
+  }
+  return true;
+}
+uint32_t bitrev(uint32_t x, uint32_t bits) {
+  uint32_t r = 0;
+  for (uint32_t i = 0; i < bits; ++i) r = (r << 1) | ((x >> i) & 1);
+  return r;
+}
+// The smallest primitive 2N-th root of unity mod q: find one root r as
+// c^((q-1)/2N) for the first c that gives order 2N, then take the minimum over
+// its odd powers (exactly the set of primitive 2N-th roots).
+uint32_t psi_of(uint32_t N, uint32_t q) {
+  uint64_t r = 0;
+  for (uint64_t c = 2; c < q; ++c) {
+    const uint64_t x = powmod(c, (q - 1) / (2ull * N), q);
+    if (powmod(x, N, q) == q - 1) {
+      r = x;
+      break;
+    }
+  }
+  const uint64_t r2 = mulmod(r, r, q);
+  uint64_t best = q, x = r;
+  for (uint32_t i = 0; i < N; ++i) {
+    best = std::min(best, x);
+    x = mulmod(x, r2, q);
+  }
+  return (uint32_t)best;
+}
+uint32_t shoup(uint32_t w, uint32_t q) { return (uint32_t)(((uint64_t)w << 32) / q); }
+
+bool log2n_ok(uint32_t l) { return l >= PIR_MIN_LOG2_N && l <= PIR_MAX_LOG2_N; }
+
+pir_status check_params(pir_ctx *ctx, const pir_params *p) {
+  if (!p) return fail(ctx, PIR_ERR_INVALID_ARG, "params is NULL");
+  if (!log2n_ok(p->log2_n))
+    return fail(ctx, PIR_ERR_UNSUPPORTED, "log2_n=%u outside [%d, %d]", p->log2_n, PIR_MIN_LOG2_N,
+                PIR_MAX_LOG2_N);
+  if (p->n_primes < 1 || p->n_primes > PIR_MAX_PRIMES)
+    return fail(ctx, PIR_ERR_UNSUPPORTED, "n_primes=%u outside [1, %d]", p->n_primes,
+                PIR_MAX_PRIMES);
+  if (p->plain_log2 < 1 || p->plain_log2 > 8)
+    return fail(ctx, PIR_ERR_UNSUPPORTED, "plain_log2=%u outside [1, 8]", p->plain_log2);
+  const uint64_t twoN = 2ull << p->log2_n;
+  for (uint32_t k = 0; k < p->n_primes; ++k) {
+    const uint32_t q = p->primes[k];
+    if (q >= (1u << PIR_PRIME_BITS) || q % twoN != 1 || !is_prime_u32(q))
+      return fail(ctx, PIR_ERR_UNSUPPORTED, "primes[%u]=%u is not a prime < 2^28 with q = 1 mod 2N",
+                  k, q);
+    for (uint32_t l = 0; l < k; ++l)
+      if (p->primes[l] == q) return fail(ctx, PIR_ERR_INVALID_ARG, "primes[%u] repeated", k);
+  }
+  return PIR_OK;
+}
+
+// ------------------------------------------------------- device memory ----
+pir_status dev_alloc(pir_ctx *ctx, void **p, size_t bytes, const char *what) {
+  if (ctx->budget && ctx->held + bytes > ctx->budget)
+    return fail(ctx, PIR_ERR_BUDGET, "%s: %zu bytes would exceed the HBM budget (%zu of %zu held)",
+                what, bytes, ctx->held, ctx->budget);
+  if (hipMalloc(p, bytes) != hipSuccess) {
+    (void)hipGetLastError();
+    *p = nullptr;
+    return fail(ctx, PIR_ERR_OUT_OF_MEMORY, "%s: hipMalloc(%zu) failed", what, bytes);
+  }
+  ctx->held += bytes;
+  return PIR_OK;
+}
+void dev_free(pir_ctx *ctx, void *p, size_t bytes) {
+  if (!p) return;
+  (void)hipFree(p);
+  ctx->held -= bytes;
+}
+
+pir_status ensure_ws(pir_ctx *ctx, size_t bytes) {
+  if (ctx->ws_bytes >= bytes) return PIR_OK;
+  HIP_OR_FAIL(ctx, hipDeviceSynchronize());
+  dev_free(ctx, ctx->ws, ctx->ws_bytes);
+  ctx->ws = nullptr;
+  ctx->ws_bytes = 0;
+  const size_t want = (bytes + (1u << 20) - 1) & ~(size_t)((1u << 20) - 1);
+  pir_status st = dev_alloc(ctx, &ctx->ws, want, "workspace");
+  if (st != PIR_OK) return st;
+  ctx->ws_bytes = want;
+  return PIR_OK;
+}
+
+// Device table of per-prime constants for (log2n, primes).
+pir_status prime_set(pir_ctx *ctx, const pir_params *p, const DevPrime **out) {
+  std::vector<uint32_t> key{p->log2_n};
+  for (uint32_t k = 0; k < p->n_primes; ++k) key.push_back(p->primes[k]);
+  auto it = ctx->prime_sets.find(key);
+  if (it != ctx->prime_sets.end()) {
+    *out = it->second;
+    return PIR_OK;
+  }
+  const uint32_t N = 1u << p->log2_n;
+  std::vector<DevPrime> host(p->n_primes);
+  for (uint32_t k = 0; k < p->n_primes; ++k) {
+    const uint32_t q = p->primes[k];
+    auto tk = std::make_pair(p->log2_n, q);
+    uint32_t *tw = nullptr;
+    auto ti = ctx->tw_tables.find(tk);
+    if (ti != ctx->tw_tables.end()) {
+      tw = ti->second;
+    } else {
+      const uint32_t psi = psi_of(N, q);
+      const uint32_t psi_inv = (uint32_t)powmod(psi, 2ull * N - 1, q);
+      std::vector<uint32_t> h(4 * (size_t)N);
+      for (uint32_t i = 0; i < N; ++i) {
+        const uint32_t br = bitrev(i, p->log2_n);
+        const uint32_t f = (uint32_t)powmod(psi, br, q), v = (uint32_t)powmod(psi_inv, br, q);
+        h[i] = f;
+        h[N + i] = shoup(f, q);
+        h[2 * N + i] = v;
+        h[3 * N + i] = shoup(v, q);
+      }
+      pir_status st = dev_alloc(ctx, (void **)&tw, h.size() * 4, "twiddle table");
+      if (st != PIR_OK) return st;
+      HIP_OR_FAIL(ctx, hipMemcpy(tw, h.data(), h.size() * 4, hipMemcpyHostToDevice));
+      ctx->tw_tables[tk] = tw;
+    }
+    DevPrime &d = host[k];
+    std::memset(&d, 0, sizeof d);
+    d.q = q;
+    d.log2n = p->log2_n;
+    d.ninv = (uint32_t)powmod(N, q - 2, q);
+    d.ninv_sh = shoup(d.ninv, q);
+    for (int s = 0; s < 7; ++s) {
+      d.w[s] = (uint32_t)powmod(2, 7ull * s, q);
+      d.w_sh[s] = shoup(d.w[s], q);
+    }
+    d.tw = tw;
+  }
+  DevPrime *dev = nullptr;
+  pir_status st = dev_alloc(ctx, (void **)&dev, sizeof(DevPrime) * host.size(), "prime table");
+  if (st != PIR_OK) return st;
+  HIP_OR_FAIL(ctx, hipMemcpy(dev, host.data(), sizeof(DevPrime) * host.size(), hipMemcpyHostToDevice));
+  ctx->prime_sets[key] = dev;
+  *out = dev;
+  return PIR_OK;
+}
+
+// Brackets one stage launch with HIP events when profiling is on.
+struct StageTimer {
+  pir_ctx *ctx;
+  hipStream_t s;
+  pir_ctx::Rec rec{};
+  bool on = false;
+  StageTimer(pir_ctx *c, hipStream_t st, uint32_t stage) : ctx(c), s(st) {
+    if (!ctx->prof) return;
+    rec.stage = stage;
+    if (hipEventCreate(&rec.a) != hipSuccess || hipEventCreate(&rec.b) != hipSuccess) return;
+    on = hipEventRecord(rec.a, s) == hipSuccess;
+  }
+  ~StageTimer() {
+    if (!on) return;
+    if (hipEventRecord(rec.b, s) == hipSuccess) ctx->pending.push_back(rec);
+  }
+};
+
+void profile_drain(pir_ctx *ctx) {
+  for (auto &r : ctx->pending) {
+    float ms = 0.f;
+    if (hipEventSynchronize(r.b) == hipSuccess && hipEventElapsedTime(&ms, r.a, r.b) == hipSuccess) {
+      ctx->stage_ms[r.stage] += ms;
+      ctx->stage_n[r.stage] += 1;
+    }
+    (void)hipEventDestroy(r.a);
+    (void)hipEventDestroy(r.b);
+  }
+  ctx->pending.clear();
+}
+
+size_t query_atom_bytes(const DbDesc &d, uint32_t B) {
+  const uint32_t n_cb = (2 * B + kCB - 1) / kCB;
+  return (size_t)d.K * d.N * d.n_ib * n_cb * kAtomBytes;
+}
+
+}  // namespace
+
+// ===================================================================== ABI ==
+extern "C" {
+
+const char *pir_status_string(pir_status s) {
+  switch (s) {
+    case PIR_OK: return "PIR_OK";
+    case PIR_ERR_INVALID_ARG: return "PIR_ERR_INVALID_ARG";
+    case PIR_ERR_UNSUPPORTED: return "PIR_ERR_UNSUPPORTED";
+    case PIR_ERR_OUT_OF_MEMORY: return "PIR_ERR_OUT_OF_MEMORY";
+    case PIR_ERR_BUDGET: return "PIR_ERR_BUDGET";
+    case PIR_ERR_DEVICE: return "PIR_ERR_DEVICE";
+    case PIR_ERR_NOT_READY: return "PIR_ERR_NOT_READY";
+  }
+  return "PIR_ERR_UNKNOWN";
+}
+
+const char *pir_version(void) { return "libpir 0.1 (gfx950)"; }
+
+pir_status pir_find_primes(uint32_t log2_n, uint32_t count, uint32_t bound_log2, uint32_t *out) {
+  if (!out || count == 0 || log2_n > 20 || bound_log2 > 31 || bound_log2 <= log2_n + 1)
+    return PIR_ERR_INVALID_ARG;
+  const uint64_t step = 2ull << log2_n;
+  uint64_t q = ((1ull << bound_log2) - 2) / step * step + 1;
+  uint32_t found = 0;
+  while (found < count && q > step) {
+    if (is_prime_u32(q)) out[found++] = (uint32_t)q;
+    q -= step;
+  }
+  return found == count ? PIR_OK : PIR_ERR_INVALID_ARG;
+}
+
+pir_status pir_params_check(const pir_params *params, uint32_t *psi_out) {
+  pir_status st = check_params(nullptr, params);
+  if (st != PIR_OK) return st;
+  if (psi_out)
+    for (uint32_t k = 0; k < params->n_primes; ++k)
+      psi_out[k] = psi_of(1u << params->log2_n, params->primes[k]);
+  return PIR_OK;
+}
+
+pir_status pir_ctx_create(int device, size_t hbm_budget_bytes, pir_ctx **out) {
+  if (!out) return PIR_ERR_INVALID_ARG;
+  *out = nullptr;
+  int n = 0;
+  if (hipGetDeviceCount(&n) != hipSuccess || device < 0 || device >= n) {
+    (void)hipGetLastError();
+    return PIR_ERR_DEVICE;
+  }
+  pir_ctx *ctx = new (std::nothrow) pir_ctx;
+  if (!ctx) return PIR_ERR_OUT_OF_MEMORY;
+  ctx->device = device;
+  ctx->budget = hbm_budget_bytes;
+  hipDeviceProp_t prop;
+  if (hipGetDeviceProperties(&prop, device) != hipSuccess) {
+    delete ctx;
+    return PIR_ERR_DEVICE;
+  }
+  ctx->num_cus = prop.multiProcessorCount;
+  *out = ctx;
+  return PIR_OK;
+}
+
+void pir_ctx_destroy(pir_ctx *ctx) {
+  if (!ctx) return;
+  DeviceGuard g(ctx->device);
+  (void)hipDeviceSynchronize();
+  profile_drain(ctx);
+  dev_free(ctx, ctx->ws, ctx->ws_bytes);
+  for (auto &kv : ctx->prime_sets) (void)hipFree(kv.second);
+  for (auto &kv : ctx->tw_tables) (void)hipFree(kv.second);
+  delete ctx;
+}
+
+const char *pir_last_error(const pir_ctx *ctx) { return ctx ? ctx->err.c_str() : "no context"; }
+
+size_t pir_ctx_device_bytes(const pir_ctx *ctx) { return ctx ? ctx->held : 0; }
+
+pir_status pir_ctx_reserve(pir_ctx *ctx, size_t bytes) {
+  if (!ctx) return PIR_ERR_INVALID_ARG;
+  DeviceGuard g(ctx->device);
+  return ensure_ws(ctx, bytes);
+}
+
+pir_status pir_db_load_ntt(pir_ctx *ctx, const pir_params *params, const uint8_t *raw,
+                           int raw_is_device, uint32_t R, uint32_t C, pir_stream stream,
+                           pir_db **out) {
+  if (!ctx || !out) return PIR_ERR_INVALID_ARG;
+  *out = nullptr;
+  pir_status st = check_params(ctx, params);
+  if (st != PIR_OK) return st;
+  if (!raw) return fail(ctx, PIR_ERR_INVALID_ARG, "raw is NULL");
+  if (R < 1 || R > PIR_MAX_R || C < 1 || C > PIR_MAX_C)
+    return fail(ctx, PIR_ERR_INVALID_ARG, "R=%u or C=%u out of range", R, C);
+  DeviceGuard g(ctx->device);
+  hipStream_t s = (hipStream_t)stream;
+  const DevPrime *primes = nullptr;
+  if ((st = prime_set(ctx, params, &primes)) != PIR_OK) return st;
+
+  const uint32_t N = 1u << params->log2_n, K = params->n_primes;
+  const uint32_t Rp = r_pad(R), Cp = c_pad(C);
+  const size_t bytes = (size_t)K * N * Rp * Cp * 4;
+  pir_db *db = new (std::nothrow) pir_db;
+  if (!db) return fail(ctx, PIR_ERR_OUT_OF_MEMORY, "host allocation failed");
+  db->ctx = ctx;
+  db->params = *params;
+  db->R = R;
+  db->C = C;
+  db->bytes = bytes;
+  if ((st = dev_alloc(ctx, (void **)&db->atoms, bytes, "database")) != PIR_OK) {
+    delete db;
+    return st;
+  }
+  // Slab of S rows (multiple of 32) with a temporary NTT-form buffer of ~256 MiB.
+  const size_t row_bytes = (size_t)K * C * N * 4;
+  uint32_t S = (uint32_t)std::max<size_t>(32, ((256u << 20) / row_bytes) / 32 * 32);
+  S = std::min(S, Rp);
+  uint32_t *tmp = nullptr;
+  uint8_t *stage = nullptr;
+  const size_t tmp_bytes = (size_t)S * row_bytes, stage_bytes = (size_t)S * C * N;
+  auto cleanup = [&](pir_status code) {
+    (void)hipStreamSynchronize(s);
+    dev_free(ctx, tmp, tmp_bytes);
+    dev_free(ctx, stage, stage_bytes);
+    if (code != PIR_OK) {
+      dev_free(ctx, db->atoms, db->bytes);
+      delete db;
+    }
+    return code;
+  };
+  if ((st = dev_alloc(ctx, (void **)&tmp, tmp_bytes, "load slab")) != PIR_OK) return cleanup(st);
+  if (!raw_is_device &&
+      (st = dev_alloc(ctx, (void **)&stage, stage_bytes, "load staging")) != PIR_OK)
+    return cleanup(st);
+  for (uint32_t i0 = 0; i0 < Rp; i0 += S) {
+    const uint32_t valid = i0 < R ? std::min(S, R - i0) : 0;
+    const uint8_t *src = raw + (size_t)i0 * C * N;
+    if (!raw_is_device) {
+      if (valid && hipMemcpyAsync(stage, src, (size_t)valid * C * N, hipMemcpyHostToDevice, s) !=
+                       hipSuccess)
+        return cleanup(fail(ctx, PIR_ERR_DEVICE, "host-to-device copy of the raw DB failed"));
+      src = stage;
+    }
+    hipError_t e = launch_lift_ntt(valid ? src : nullptr, tmp, S, valid, C, K, params->log2_n,
+                                   primes, s);
+    if (e == hipSuccess) e = launch_pack_db(tmp, db->atoms, i0, S, R, C, N, K, s);
+    if (e != hipSuccess)
+      return cleanup(fail(ctx, PIR_ERR_DEVICE, "DB transform launch failed: %s", hipGetErrorString(e)));
+  }
+  if (hipStreamSynchronize(s) != hipSuccess)
+    return cleanup(fail(ctx, PIR_ERR_DEVICE, "DB transform failed"));
+  DbDesc &d = db->desc;
+  d.atoms = db->atoms;
+  d.primes = primes;
+  d.R = R;
+  d.C = C;
+  d.N = N;
+  d.K = K;
+  d.log2n = params->log2_n;
+  d.n_jb = Cp / kJB;
+  d.n_ib = Rp / kIB;
+  *out = db;
+  return cleanup(PIR_OK);
+}
+
+pir_status pir_db_info(const pir_db *db, pir_params *params, uint32_t *R, uint32_t *C,
+                       size_t *device_bytes) {
+  if (!db) return PIR_ERR_INVALID_ARG;
+  if (params) *params = db->params;
+  if (R) *R = db->R;
+  if (C) *C = db->C;
+  if (device_bytes) *device_bytes = db->bytes;
+  return PIR_OK;
+}
+
+pir_status pir_db_read_ntt(pir_ctx *ctx, const pir_db *db, uint32_t i0, uint32_t ni,
+                           uint32_t j0, uint32_t nj, uint32_t *out, pir_stream stream) {
+  if (!ctx || !db || !out) return fail(ctx, PIR_ERR_INVALID_ARG, "null argument");
+  if (db->ctx != ctx) return fail(ctx, PIR_ERR_INVALID_ARG, "database belongs to another context");
+  if ((uint64_t)i0 + ni > db->R || (uint64_t)j0 + nj > db->C)
+    return fail(ctx, PIR_ERR_INVALID_ARG, "rows/columns out of range");
+  DeviceGuard g(ctx->device);
+  HIP_OR_FAIL(ctx, launch_read_db(db->desc, i0, ni, j0, nj, out, (hipStream_t)stream));
+  return PIR_OK;
+}
+
+void pir_db_free(pir_db *db) {
+  if (!db) return;
+  DeviceGuard g(db->ctx->device);
+  (void)hipDeviceSynchronize();
+  dev_free(db->ctx, db->atoms, db->bytes);
+  delete db;
+}
+
+static pir_status ntt_common(pir_ctx *ctx, const pir_params *params, uint32_t *polys,
+                             size_t n_polys, pir_stream stream, bool inverse) {
+  if (!ctx) return PIR_ERR_INVALID_ARG;
+  pir_status st = check_params(ctx, params);
+  if (st != PIR_OK) return st;
+  if (!polys && n_polys) return fail(ctx, PIR_ERR_INVALID_ARG, "polys is NULL");
+  if (n_polys > (size_t)0x7fffffff / params->n_primes)
+    return fail(ctx, PIR_ERR_INVALID_ARG, "too many polynomials");
+  DeviceGuard g(ctx->device);
+  const DevPrime *primes = nullptr;
+  if ((st = prime_set(ctx, params, &primes)) != PIR_OK) return st;
+  HIP_OR_FAIL(ctx, launch_ntt(polys, n_polys * params->n_primes, params->n_primes, params->log2_n,
+                              primes, inverse, (hipStream_t)stream));
+  return PIR_OK;
+}
+
+pir_status pir_ntt(pir_ctx *ctx, const pir_params *params, uint32_t *polys, size_t n_polys,
+                   pir_stream stream) {
+  return ntt_common(ctx, params, polys, n_polys, stream, false);
+}
+
+pir_status pir_intt(pir_ctx *ctx, const pir_params *params, uint32_t *polys, size_t n_polys,
+                    pir_stream stream) {
+  return ntt_common(ctx, params, polys, n_polys, stream, true);
+}
+
+pir_status pir_db_mul(pir_ctx *ctx, const pir_db *db, const uint32_t *query_ntt, uint32_t B,
+                      uint32_t *answer_ntt, pir_stream stream) {
+  if (!ctx) return PIR_ERR_INVALID_ARG;
+  if (!db || !query_ntt || !answer_ntt) return fail(ctx, PIR_ERR_INVALID_ARG, "null argument");
+  if (db->ctx != ctx) return fail(ctx, PIR_ERR_INVALID_ARG, "database belongs to another context");
+  if (B < 1 || B > PIR_MAX_BATCH) return fail(ctx, PIR_ERR_INVALID_ARG, "B=%u out of range", B);
+  DeviceGuard g(ctx->device);
+  const size_t qa = query_atom_bytes(db->desc, B);
+  pir_status st = ensure_ws(ctx, qa);
+  if (st != PIR_OK) return st;
+  hipStream_t s = (hipStream_t)stream;
+  uint8_t *qatoms = (uint8_t *)ctx->ws;
+  {
+    StageTimer tm(ctx, s, PIR_STAGE_PACK);
+    HIP_OR_FAIL(ctx, launch_pack_query(query_ntt, qatoms, B, db->R, db->desc.N, db->desc.K, s));
+  }
+  ScanJob job{db->desc, qatoms, answer_ntt, B};
+  {
+    StageTimer tm(ctx, s, PIR_STAGE_SCAN);
+    HIP_OR_FAIL(ctx, launch_scan(job, ctx->num_cus, s));
+  }
+  return PIR_OK;
+}
+
+pir_status pir_answer_batch(pir_ctx *ctx, const pir_job *jobs, size_t n_jobs, pir_stream stream) {
+  if (!ctx) return PIR_ERR_INVALID_ARG;
+  if (!jobs && n_jobs) return fail(ctx, PIR_ERR_INVALID_ARG, "jobs is NULL");
+  size_t max_q = 0, sum_atoms = 0;
+  for (size_t n = 0; n < n_jobs; ++n) {
+    const pir_job &j = jobs[n];
+    if (!j.db || !j.query_coeff || !j.answer_coeff)
+      return fail(ctx, PIR_ERR_INVALID_ARG, "job %zu has a null pointer", n);
+    if (j.db->ctx != ctx)
+      return fail(ctx, PIR_ERR_INVALID_ARG, "job %zu: database belongs to another context", n);
+    if (j.B < 1 || j.B > PIR_MAX_BATCH)
+      return fail(ctx, PIR_ERR_INVALID_ARG, "job %zu: B=%u out of range", n, j.B);
+    const DbDesc &d = j.db->desc;
+    max_q = std::max(max_q, (size_t)j.B * d.R * 2 * d.K * d.N * 4);
+    sum_atoms += (query_atom_bytes(d, j.B) + 255) & ~(size_t)255;
+  }
+  if (n_jobs == 0) return PIR_OK;
+  DeviceGuard g(ctx->device);
+  const size_t q_region = (max_q + 255) & ~(size_t)255;
+  pir_status st = ensure_ws(ctx, q_region + sum_atoms);
+  if (st != PIR_OK) return st;
+  hipStream_t s = (hipStream_t)stream;
+  uint32_t *qntt = (uint32_t *)ctx->ws;
+  uint8_t *atoms = (uint8_t *)ctx->ws + q_region;
+  std::vector<ScanJob> sj(n_jobs);
+  for (size_t n = 0; n < n_jobs; ++n) {
+    const pir_job &j = jobs[n];
+    const DbDesc &d = j.db->desc;
+    {
+      StageTimer tm(ctx, s, PIR_STAGE_NTT);
+      HIP_OR_FAIL(ctx, launch_ntt_copy(j.query_coeff, qntt, (size_t)j.B * d.R * 2 * d.K, d.K,
+                                       d.log2n, d.primes, s));
+    }
+    {
+      StageTimer tm(ctx, s, PIR_STAGE_PACK);
+      HIP_OR_FAIL(ctx, launch_pack_query(qntt, atoms, j.B, d.R, d.N, d.K, s));
+    }
+    sj[n] = ScanJob{d, atoms, j.answer_coeff, j.B};
+    atoms += (query_atom_bytes(d, j.B) + 255) & ~(size_t)255;
+  }
+  for (size_t n = 0; n < n_jobs; ++n) {
+    StageTimer tm(ctx, s, PIR_STAGE_SCAN);
+    HIP_OR_FAIL(ctx, launch_scan(sj[n], ctx->num_cus, s));
+  }
+  for (size_t n = 0; n < n_jobs; ++n) {
+    const DbDesc &d = sj[n].db;
+    StageTimer tm(ctx, s, PIR_STAGE_INTT);
+    HIP_OR_FAIL(ctx, launch_ntt(sj[n].out, (size_t)sj[n].B * d.C * 2 * d.K, d.K, d.log2n, d.primes,
+                                true, s));
+  }
+  return PIR_OK;
+}
+
+pir_status pir_profile_enable(pir_ctx *ctx, int enable) {
+  if (!ctx) return PIR_ERR_INVALID_ARG;
+  DeviceGuard g(ctx->device);
+  profile_drain(ctx);
+  for (int i = 0; i < PIR_N_STAGES; ++i) ctx->stage_ms[i] = 0, ctx->stage_n[i] = 0;
+  ctx->prof = enable != 0;
+  return PIR_OK;
+}
+
+pir_status pir_profile_read(pir_ctx *ctx, uint32_t stage, double *total_ms, uint64_t *launches) {
+  if (!ctx || stage >= PIR_N_STAGES) return PIR_ERR_INVALID_ARG;
+  DeviceGuard g(ctx->device);
+  profile_drain(ctx);
+  if (total_ms) *total_ms = ctx->stage_ms[stage];
+  if (launches) *launches = ctx->stage_n[stage];
+  return PIR_OK;
+}
+
+}  // extern "C"

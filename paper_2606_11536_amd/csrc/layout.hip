@@ -1,0 +1,161 @@
+// Layout transposition between polynomial-major NTT form and the slot-major,
+// limb-planar atoms the scan consumes (paper: Sec. 4.2, layout
+// transposition between NTT-friendly and GEMM-friendly layouts).
+//
+// Each packing workgroup stages a 32 (i) x 8 (j or column) x 32 (t) tile of
+// residues in LDS -- read as 128-byte runs along t -- and writes 32 whole
+// 1 KiB atoms, one per slot t, so both sides of the transposition move full
+// contiguous lines.
+#include "device_util.h"
+#include "pir_internal.h"
+
+namespace pir {
+namespace {
+
+constexpr int kPad = 33;  // LDS row pitch (words) of the t dimension
+
+// slab: [K][S][C][N] NTT-form residues of rows i0 .. i0 + S - 1.
+__global__ __launch_bounds__(256) void k_pack_db(const uint32_t *__restrict__ slab,
+                                                 uint8_t *__restrict__ atoms, uint32_t ib_first,
+                                                 uint32_t S, uint32_t C, uint32_t N,
+                                                 uint32_t n_jb, uint32_t n_ib) {
+  __shared__ uint32_t lds[32 * 8 * kPad];
+  const uint32_t tid = threadIdx.x;
+  const uint32_t t0 = blockIdx.x * 32;
+  const uint32_t jb = blockIdx.y;
+  const uint32_t ib_per_slab = S / 32;
+  const uint32_t k = blockIdx.z / ib_per_slab;
+  const uint32_t ibl = blockIdx.z % ib_per_slab;
+  const uint32_t ib = ib_first + ibl;
+  if (ib >= n_ib) return;  // slab rows past R_pad: nothing to write
+
+  const uint32_t tt = tid & 31, p = tid >> 5;
+#pragma unroll 4
+  for (uint32_t r = 0; r < 32; ++r) {
+    const uint32_t pi = p + 8 * r;
+    const uint32_t il = pi >> 3, jl = pi & 7;
+    const uint32_t j = jb * 8 + jl;
+    uint32_t v = 0;
+    if (j < C) v = slab[(((size_t)k * S + ibl * 32 + il) * C + j) * N + t0 + tt];
+    lds[(il * 8 + jl) * kPad + tt] = v;
+  }
+  __syncthreads();
+  uint4 *out = reinterpret_cast<uint4 *>(atoms);
+#pragma unroll 2
+  for (uint32_t r = 0; r < 8; ++r) {
+    const uint32_t w = tid + 256 * r;
+    const uint32_t tl = w >> 6, lane = w & 63;
+    const uint32_t g = lane >> 5, m = lane & 31, jl = m >> 2, a = m & 3;
+    uint32_t word[4];
+#pragma unroll
+    for (int q4 = 0; q4 < 4; ++q4) {
+      uint32_t acc = 0;
+#pragma unroll
+      for (int e = 0; e < 4; ++e) {
+        const uint32_t v = lds[((16 * g + 4 * q4 + e) * 8 + jl) * kPad + tl];
+        acc |= ((v >> (7 * a)) & 127u) << (8 * e);
+      }
+      word[q4] = acc;
+    }
+    const size_t atom = (((size_t)k * N + t0 + tl) * n_jb + jb) * n_ib + ib;
+    out[atom * 64 + lane] = make_uint4(word[0], word[1], word[2], word[3]);
+  }
+}
+
+// Canonical read-back: out[ii][jj][k][t] for rows i0 + ii, columns j0 + jj.
+__global__ void k_read_db(DbDesc db, uint32_t i0, uint32_t ni, uint32_t j0, uint32_t nj,
+                          uint32_t *__restrict__ out) {
+  const size_t total = (size_t)ni * nj * db.K * db.N;
+  for (size_t idx = blockIdx.x * (size_t)blockDim.x + threadIdx.x; idx < total;
+       idx += (size_t)gridDim.x * blockDim.x) {
+    const uint32_t t = idx % db.N;
+    size_t rest = idx / db.N;
+    const uint32_t k = rest % db.K;
+    rest /= db.K;
+    const uint32_t jj = rest % nj;
+    const uint32_t ii = rest / nj;
+    const uint32_t i = i0 + ii, j = j0 + jj;
+    const size_t atom = (((size_t)k * db.N + t) * db.n_jb + j / 8) * db.n_ib + i / 32;
+    const uint32_t lane0 = ((i % 32) >> 4) * 32 + (j % 8) * 4;
+    const uint8_t *p = db.atoms + atom * kAtomBytes + (i % 16);
+    uint32_t v = 0;
+#pragma unroll
+    for (uint32_t a = 0; a < 4; ++a) v |= (uint32_t)p[(lane0 + a) * 16] << (7 * a);
+    out[idx] = v;
+  }
+}
+
+// q: [B][R][2][K][N] NTT form -> query atoms [K][N][n_ib][n_cb].
+__global__ __launch_bounds__(256) void k_pack_query(const uint32_t *__restrict__ q,
+                                                    uint8_t *__restrict__ qatoms, uint32_t B,
+                                                    uint32_t R, uint32_t N, uint32_t K,
+                                                    uint32_t n_ib, uint32_t n_cb) {
+  __shared__ uint32_t lds[32 * 8 * kPad];
+  const uint32_t tid = threadIdx.x;
+  const uint32_t t0 = blockIdx.x * 32;
+  const uint32_t ib = blockIdx.y;
+  const uint32_t k = blockIdx.z / n_cb, cb = blockIdx.z % n_cb;
+  const uint32_t tt = tid & 31, p = tid >> 5;
+  const uint32_t ncol = 2 * B;
+#pragma unroll 4
+  for (uint32_t r = 0; r < 32; ++r) {
+    const uint32_t pi = p + 8 * r;
+    const uint32_t il = pi >> 3, cc = pi & 7;
+    const uint32_t i = ib * 32 + il, col = cb * 8 + cc;
+    uint32_t v = 0;
+    if (i < R && col < ncol)
+      v = q[((((size_t)(col >> 1) * R + i) * 2 + (col & 1)) * K + k) * N + t0 + tt];
+    lds[(il * 8 + cc) * kPad + tt] = v;
+  }
+  __syncthreads();
+  uint4 *out = reinterpret_cast<uint4 *>(qatoms);
+#pragma unroll 2
+  for (uint32_t r = 0; r < 8; ++r) {
+    const uint32_t w = tid + 256 * r;
+    const uint32_t tl = w >> 6, lane = w & 63;
+    const uint32_t g = lane >> 5, n = lane & 31, cc = n >> 2, b = n & 3;
+    uint32_t word[4];
+#pragma unroll
+    for (int q4 = 0; q4 < 4; ++q4) {
+      uint32_t acc = 0;
+#pragma unroll
+      for (int e = 0; e < 4; ++e) {
+        const uint32_t v = lds[((16 * g + 4 * q4 + e) * 8 + cc) * kPad + tl];
+        acc |= ((v >> (7 * b)) & 127u) << (8 * e);
+      }
+      word[q4] = acc;
+    }
+    const size_t atom = (((size_t)k * N + t0 + tl) * n_ib + ib) * n_cb + cb;
+    out[atom * 64 + lane] = make_uint4(word[0], word[1], word[2], word[3]);
+  }
+}
+
+}  // namespace
+
+hipError_t launch_pack_db(const uint32_t *ntt_slab, uint8_t *atoms, uint32_t i0, uint32_t S,
+                          uint32_t R, uint32_t C, uint32_t N, uint32_t K, hipStream_t s) {
+  if (S % 32 != 0 || i0 % 32 != 0 || N % 32 != 0) return hipErrorInvalidValue;
+  const uint32_t n_jb = c_pad(C) / kJB, n_ib = r_pad(R) / kIB;
+  const dim3 grid(N / 32, n_jb, K * (S / 32));
+  k_pack_db<<<grid, 256, 0, s>>>(ntt_slab, atoms, i0 / 32, S, C, N, n_jb, n_ib);
+  return hipGetLastError();
+}
+
+hipError_t launch_read_db(const DbDesc &db, uint32_t i0, uint32_t ni, uint32_t j0, uint32_t nj,
+                          uint32_t *out, hipStream_t s) {
+  const size_t total = (size_t)ni * nj * db.K * db.N;
+  if (total == 0) return hipSuccess;
+  const size_t blocks = (total + 255) / 256;
+  k_read_db<<<(unsigned)(blocks < 65536 ? blocks : 65536), 256, 0, s>>>(db, i0, ni, j0, nj, out);
+  return hipGetLastError();
+}
+
+hipError_t launch_pack_query(const uint32_t *q_ntt, uint8_t *qatoms, uint32_t B, uint32_t R,
+                             uint32_t N, uint32_t K, hipStream_t s) {
+  const uint32_t n_ib = r_pad(R) / kIB, n_cb = (2 * B + kCB - 1) / kCB;
+  const dim3 grid(N / 32, n_ib, K * n_cb);
+  k_pack_query<<<grid, 256, 0, s>>>(q_ntt, qatoms, B, R, N, K, n_ib, n_cb);
+  return hipGetLastError();
+}
+
+}  // namespace pir

@@ -1,0 +1,103 @@
+// Internal declarations of libpir: device-side constants, the tile layouts
+// of the scan, and the launchers the host API calls.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stddef.h>
+#include <stdint.h>
+
+#include "../../include/pir.h"
+
+namespace pir {
+
+// ---------------------------------------------------------------------------
+// Per-prime constants kept in device memory (one entry per RNS prime).
+//   tw: [4][N] uint32 -- psi^brv(i), its Shoup companion, psi^-brv(i), its
+//   Shoup companion, for i in [0, N); brv over log2 N bits.
+//   w:  limb weights 2^(7s) mod q for s = 0..6 (index 7 unused), w_sh their
+//   Shoup companions floor(w * 2^32 / q).
+// ---------------------------------------------------------------------------
+struct DevPrime {
+  uint32_t q;
+  uint32_t ninv, ninv_sh;
+  uint32_t log2n;
+  uint32_t w[8];
+  uint32_t w_sh[8];
+  const uint32_t *tw;
+};
+
+// ---------------------------------------------------------------------------
+// Scan layouts.  Both operands of the scan are stored as 1 KiB "atoms", each
+// holding exactly the bytes one 64-lane wave feeds to one
+// v_mfma_i32_32x32x32_i8 operand: lane l owns bytes [16 l, 16 l + 16).
+//
+// An element x < 2^28 is split into four 7-bit limbs x = sum_a x_a 2^(7a),
+// x_a in [0, 127], each a non-negative int8.
+//
+// Database atom (k, t, jb, ib): lane l = 32 g + 4 jl + a (g < 2, jl < 8,
+// a < 4) holds limb a of D_t[j = 8 jb + jl][i = 32 ib + 16 g + e], e < 16,
+// where D_t[j][i] is slot t (prime k) of NTT(lift(DB[i][j])).  Atom order
+// [k][t][jb][ib]; jb < C_pad/8, ib < R_pad/32 (R_pad a multiple of 64).
+//
+// Query atom (k, t, ib, cb): lane l = 32 g + 4 cc + b holds limb b of
+// Q_t[i = 32 ib + 16 g + e][col = 8 cb + cc], col = 2 * query + component.
+// Atom order [k][t][ib][cb]; cb < ceil(2B/8).
+//
+// Because lane l feeds the same 16 k-indices of the contraction to the A and
+// B operands, the MFMA's internal order of k is irrelevant: every row of A is
+// matched with the same i-range of B.
+// ---------------------------------------------------------------------------
+constexpr uint32_t kAtomBytes = 1024;
+constexpr uint32_t kJB = 8;    // database rows j per atom
+constexpr uint32_t kIB = 32;   // contraction indices i per atom
+constexpr uint32_t kRAlign = 64;
+constexpr uint32_t kCB = 8;    // query columns per atom
+
+inline uint32_t r_pad(uint32_t R) { return (R + kRAlign - 1) / kRAlign * kRAlign; }
+inline uint32_t c_pad(uint32_t C) { return (C + kJB - 1) / kJB * kJB; }
+
+// Device-side description of one loaded database for the scan kernels.
+struct DbDesc {
+  const uint8_t *atoms;    // database atoms
+  const DevPrime *primes;  // [K]
+  uint32_t R, C, N, K, log2n;
+  uint32_t n_jb, n_ib;     // C_pad / 8, R_pad / 32
+};
+
+// ---------------------------------------------------------------------------
+// Launchers (implemented in the .hip files).  All are asynchronous on `s`.
+// ---------------------------------------------------------------------------
+// In-place forward / inverse NTT of rows [n_rows][N], row r uses prime r % K.
+hipError_t launch_ntt(uint32_t *data, size_t n_rows, uint32_t K, uint32_t log2n,
+                      const DevPrime *primes, bool inverse, hipStream_t s);
+// Out-of-place forward NTT: src and dst both [n_rows][N] (row r -> prime r % K).
+hipError_t launch_ntt_copy(const uint32_t *src, uint32_t *dst, size_t n_rows, uint32_t K,
+                           uint32_t log2n, const DevPrime *primes, hipStream_t s);
+// Lift + forward NTT of a slab of raw database rows: raw [S][C][N] uint8 ->
+// out [K][S][C][N] uint32.  Rows >= s_valid are taken as zero.
+hipError_t launch_lift_ntt(const uint8_t *raw, uint32_t *out, uint32_t S, uint32_t s_valid,
+                           uint32_t C, uint32_t K, uint32_t log2n, const DevPrime *primes,
+                           hipStream_t s);
+// Pack a slab (rows [i0, i0 + S)) of NTT-form database [K][S][C][N] into atoms.
+hipError_t launch_pack_db(const uint32_t *ntt_slab, uint8_t *atoms, uint32_t i0, uint32_t S,
+                          uint32_t R, uint32_t C, uint32_t N, uint32_t K, hipStream_t s);
+// Read back canonical NTT-form database polys [ni][nj][K][N].
+hipError_t launch_read_db(const DbDesc &db, uint32_t i0, uint32_t ni, uint32_t j0, uint32_t nj,
+                          uint32_t *out, hipStream_t s);
+// Pack NTT-form queries [B][R][2][K][N] into query atoms (R_pad rows).
+hipError_t launch_pack_query(const uint32_t *q_ntt, uint8_t *qatoms, uint32_t B, uint32_t R,
+                             uint32_t N, uint32_t K, hipStream_t s);
+
+// One scan job for the scan kernels.
+struct ScanJob {
+  DbDesc db;
+  const uint8_t *qatoms;   // query atoms of this job
+  uint32_t *out;           // answer NTT form [B][C][2][K][N]
+  uint32_t B;
+};
+
+// The scan for one job: picks the batch-1 streaming kernel or the MFMA
+// batched kernel by B.
+hipError_t launch_scan(const ScanJob &job, int num_cus, hipStream_t s);
+
+}  // namespace pir

@@ -1,0 +1,269 @@
+"""ctypes binding of libpir (include/pir.h): argument marshalling only.
+
+Every step of the scan runs in libpir's HIP kernels; this module converts
+Python/torch arguments to the C ABI and raises ``PirError`` on a non-OK
+status.  Device buffers are torch tensors on the ROCm device (uint32 data is
+held in int32 storage); streams default to torch's current stream.
+
+If ``libpir.so`` has not been built the import fails loudly: there is no
+fallback implementation.
+"""
+
+from __future__ import annotations
+
+import ctypes as ct
+import os
+import weakref
+from dataclasses import dataclass, field
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libpir.so")
+
+MAX_PRIMES = 4
+STATUS = {
+    0: "PIR_OK", 1: "PIR_ERR_INVALID_ARG", 2: "PIR_ERR_UNSUPPORTED", 3: "PIR_ERR_OUT_OF_MEMORY",
+    4: "PIR_ERR_BUDGET", 5: "PIR_ERR_DEVICE", 6: "PIR_ERR_NOT_READY",
+}
+
+# Declared C functions: name -> (restype, argtypes).  Mirrors include/pir.h.
+_P = ct.c_void_p
+_U32 = ct.c_uint32
+_U32P = ct.POINTER(ct.c_uint32)
+
+
+class CParams(ct.Structure):
+    _fields_ = [("log2_n", ct.c_uint32), ("n_primes", ct.c_uint32),
+                ("primes", ct.c_uint32 * MAX_PRIMES), ("plain_log2", ct.c_uint32)]
+
+
+class CJob(ct.Structure):
+    _fields_ = [("db", ct.c_void_p), ("B", ct.c_uint32), ("query_coeff", ct.c_void_p),
+                ("answer_coeff", ct.c_void_p)]
+
+
+SIGNATURES = {
+    "pir_status_string": (ct.c_char_p, [ct.c_int]),
+    "pir_version": (ct.c_char_p, []),
+    "pir_find_primes": (ct.c_int, [_U32, _U32, _U32, _U32P]),
+    "pir_params_check": (ct.c_int, [ct.POINTER(CParams), _U32P]),
+    "pir_ctx_create": (ct.c_int, [ct.c_int, ct.c_size_t, ct.POINTER(ct.c_void_p)]),
+    "pir_ctx_destroy": (None, [_P]),
+    "pir_last_error": (ct.c_char_p, [_P]),
+    "pir_ctx_device_bytes": (ct.c_size_t, [_P]),
+    "pir_ctx_reserve": (ct.c_int, [_P, ct.c_size_t]),
+    "pir_db_load_ntt": (ct.c_int, [_P, ct.POINTER(CParams), _P, ct.c_int, _U32, _U32, _P,
+                                   ct.POINTER(ct.c_void_p)]),
+    "pir_db_info": (ct.c_int, [_P, ct.POINTER(CParams), _U32P, _U32P,
+                               ct.POINTER(ct.c_size_t)]),
+    "pir_db_read_ntt": (ct.c_int, [_P, _P, _U32, _U32, _U32, _U32, _P, _P]),
+    "pir_db_free": (None, [_P]),
+    "pir_ntt": (ct.c_int, [_P, ct.POINTER(CParams), _P, ct.c_size_t, _P]),
+    "pir_intt": (ct.c_int, [_P, ct.POINTER(CParams), _P, ct.c_size_t, _P]),
+    "pir_db_mul": (ct.c_int, [_P, _P, _P, _U32, _P, _P]),
+    "pir_answer_batch": (ct.c_int, [_P, ct.POINTER(CJob), ct.c_size_t, _P]),
+    "pir_profile_enable": (ct.c_int, [_P, ct.c_int]),
+    "pir_profile_read": (ct.c_int, [_P, _U32, ct.POINTER(ct.c_double),
+                                    ct.POINTER(ct.c_uint64)]),
+}
+
+STAGES = {"ntt": 0, "pack": 1, "scan": 2, "intt": 3}
+
+
+class PirError(RuntimeError):
+    def __init__(self, status: int, msg: str):
+        super().__init__(f"{STATUS.get(status, status)}: {msg}")
+        self.status = status
+
+
+def _load() -> ct.CDLL:
+    if not os.path.exists(LIB_PATH):
+        raise ImportError(f"{LIB_PATH} is not built: run `python -m paper_2606_11536_amd.build`")
+    lib = ct.CDLL(LIB_PATH)
+    for name, (res, args) in SIGNATURES.items():
+        fn = getattr(lib, name)
+        fn.restype = res
+        fn.argtypes = args
+    return lib
+
+
+lib = _load()
+
+
+def _check(st: int, ctx=None) -> None:
+    if st != 0:
+        msg = lib.pir_last_error(ctx).decode() if ctx else ""
+        raise PirError(st, msg or lib.pir_status_string(st).decode())
+
+
+@dataclass
+class Params:
+    """RNS parameters: N = 2**log2_n, primes q_k, p = 2**plain_log2."""
+    log2_n: int
+    primes: list[int]
+    plain_log2: int = 8
+    _c: CParams = field(default=None, repr=False, compare=False)
+
+    @property
+    def N(self) -> int:
+        return 1 << self.log2_n
+
+    @property
+    def K(self) -> int:
+        return len(self.primes)
+
+    def c(self) -> CParams:
+        if self._c is None:
+            arr = (ct.c_uint32 * MAX_PRIMES)(*(list(self.primes) + [0] * (MAX_PRIMES - self.K)))
+            self._c = CParams(self.log2_n, self.K, arr, self.plain_log2)
+        return self._c
+
+
+def find_primes(log2_n: int, count: int, bound_log2: int = 28) -> list[int]:
+    out = (ct.c_uint32 * count)()
+    _check(lib.pir_find_primes(log2_n, count, bound_log2, out))
+    return list(out)
+
+
+def params_check(params: Params) -> list[int]:
+    """Validate; return psi_k for every prime."""
+    out = (ct.c_uint32 * MAX_PRIMES)()
+    _check(lib.pir_params_check(ct.byref(params.c()), out))
+    return list(out)[: params.K]
+
+
+def _stream(stream):
+    if stream is None:
+        import torch
+        return ct.c_void_p(torch.cuda.current_stream().cuda_stream)
+    if isinstance(stream, int):
+        return ct.c_void_p(stream)
+    return ct.c_void_p(stream.cuda_stream)
+
+
+def _ptr(t) -> ct.c_void_p:
+    return ct.c_void_p(t.data_ptr())
+
+
+class Database:
+    """A device-resident NTT-form database owned by libpir."""
+
+    def __init__(self, ctx: "Context", handle: ct.c_void_p, params: Params, R: int, C: int):
+        self.ctx, self.handle, self.params, self.R, self.C = ctx, handle, params, R, C
+
+    @property
+    def device_bytes(self) -> int:
+        n = ct.c_size_t()
+        _check(lib.pir_db_info(self.handle, None, None, None, ct.byref(n)))
+        return n.value
+
+    def read_ntt(self, i0: int, ni: int, j0: int, nj: int, stream=None):
+        """Canonical NTT form of rows [i0, i0+ni) x cols [j0, j0+nj): int32 tensor [ni][nj][K][N]."""
+        import torch
+        out = torch.empty((ni, nj, self.params.K, self.params.N), dtype=torch.int32,
+                          device=f"cuda:{self.ctx.device}")
+        _check(lib.pir_db_read_ntt(self.ctx.handle, self.handle, i0, ni, j0, nj, _ptr(out),
+                                   _stream(stream)), self.ctx.handle)
+        return out
+
+    def free(self) -> None:
+        if self.handle and self.ctx.handle:
+            lib.pir_db_free(self.handle)
+        self.handle = None
+
+    def __del__(self):
+        try:
+            self.free()
+        except Exception:
+            pass
+
+
+class Context:
+    """One libpir context on one device (tables, workspace, HBM budget)."""
+
+    def __init__(self, device: int = 0, hbm_budget_bytes: int = 0):
+        h = ct.c_void_p()
+        self.handle = None
+        _check(lib.pir_ctx_create(device, hbm_budget_bytes, ct.byref(h)))
+        self.handle, self.device = h, device
+        self._dbs = weakref.WeakSet()
+
+    def close(self) -> None:
+        """Free this context's databases, then the context."""
+        if self.handle:
+            for db in list(self._dbs):
+                db.free()
+            lib.pir_ctx_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+    @property
+    def device_bytes(self) -> int:
+        return lib.pir_ctx_device_bytes(self.handle)
+
+    def reserve(self, nbytes: int) -> None:
+        _check(lib.pir_ctx_reserve(self.handle, nbytes), self.handle)
+
+    def load_db(self, params: Params, raw, R: int, C: int, stream=None) -> Database:
+        """Offline transform of a raw [R][C][N] uint8 database (numpy array or torch tensor)."""
+        h = ct.c_void_p()
+        if hasattr(raw, "data_ptr"):
+            is_dev = int(raw.is_cuda)
+            assert raw.is_contiguous() and raw.numel() == R * C * params.N
+            ptr = ct.c_void_p(raw.data_ptr())
+        else:
+            import numpy as np
+            raw = np.ascontiguousarray(raw, dtype=np.uint8)
+            assert raw.size == R * C * params.N
+            is_dev = 0
+            ptr = raw.ctypes.data_as(ct.c_void_p)
+        _check(lib.pir_db_load_ntt(self.handle, ct.byref(params.c()), ptr, is_dev, R, C,
+                                   _stream(stream), ct.byref(h)), self.handle)
+        db = Database(self, h, params, R, C)
+        self._dbs.add(db)
+        return db
+
+    def ntt(self, params: Params, polys, n_polys: int | None = None, stream=None) -> None:
+        """In-place forward NTT of [n_polys][K][N] residues (device tensor)."""
+        n = polys.numel() // (params.K * params.N) if n_polys is None else n_polys
+        _check(lib.pir_ntt(self.handle, ct.byref(params.c()), _ptr(polys), n, _stream(stream)),
+               self.handle)
+
+    def intt(self, params: Params, polys, n_polys: int | None = None, stream=None) -> None:
+        """In-place inverse NTT (with N^-1) of [n_polys][K][N] residues (device tensor)."""
+        n = polys.numel() // (params.K * params.N) if n_polys is None else n_polys
+        _check(lib.pir_intt(self.handle, ct.byref(params.c()), _ptr(polys), n, _stream(stream)),
+               self.handle)
+
+    def db_mul(self, db: Database, query_ntt, B: int, answer_ntt, stream=None) -> None:
+        """NTT-form scan: query [B][R][2][K][N] -> answer [B][C][2][K][N] (device tensors)."""
+        _check(lib.pir_db_mul(self.handle, db.handle, _ptr(query_ntt), B, _ptr(answer_ntt),
+                              _stream(stream)), self.handle)
+
+    def answer_batch(self, jobs, stream=None) -> None:
+        """Fused batch: jobs = [(db, B, query_coeff, answer_coeff), ...] (coefficient form)."""
+        arr = (CJob * len(jobs))()
+        for n, (db, B, qc, ac) in enumerate(jobs):
+            arr[n] = CJob(db.handle, B, qc.data_ptr(), ac.data_ptr())
+        _check(lib.pir_answer_batch(self.handle, arr, len(jobs), _stream(stream)), self.handle)
+
+    def profile(self, enable: bool = True) -> None:
+        """Turn per-stage HIP-event timing on (resets the sums) or off."""
+        _check(lib.pir_profile_enable(self.handle, int(enable)), self.handle)
+
+    def profile_read(self, stage: str) -> tuple[float, int]:
+        """(summed ms, launches) of a stage since profiling was enabled; waits for the events."""
+        ms, n = ct.c_double(), ct.c_uint64()
+        _check(lib.pir_profile_read(self.handle, STAGES[stage], ct.byref(ms), ct.byref(n)),
+               self.handle)
+        return ms.value, n.value
