@@ -103,7 +103,8 @@ pir_status pir_ctx_create(int device, size_t hbm_budget_bytes, pir_ctx **out);
 /* Release the context (after freeing its databases).  Waits for the device. */
 void pir_ctx_destroy(pir_ctx *ctx);
 
-/* Text of the last error on `ctx` (valid until the next call on it). */
+/* Text of the last error on `ctx` (valid until the next call on it); with
+ * ctx == NULL, the last failure of a call that had no context (this thread). */
 const char *pir_last_error(const pir_ctx *ctx);
 
 /* Device bytes the context holds right now (databases + workspace). */

@@ -23,6 +23,9 @@ ARCH = os.environ.get("PIR_OFFLOAD_ARCH", "gfx950")
 HIPCC = shutil.which("hipcc") or "/opt/rocm/bin/hipcc"
 FLAGS = [
     f"--offload-arch={ARCH}", "-O3", "-fPIC", "-std=c++17",
+    # code object v5: loadable by both the ROCm 7.2 runtime and the HIP runtime
+    # bundled with PyTorch (ROCm 7.0), which is the one in use when torch is loaded
+    "-mcode-object-version=5",
     "-I", os.path.join(ROOT, "include"),
     # packed fp32 instructions stay off: the scan and NTT are integer code and
     # some packed-fp32 forms have been unreliable on this part

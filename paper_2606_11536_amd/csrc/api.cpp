@@ -50,16 +50,17 @@ struct pir_db {
 
 namespace {
 
+// Message of the last failure that had no context to hold it (per thread).
+thread_local std::string g_noctx_err;
+
 // ---------------------------------------------------------------- errors --
 pir_status fail(pir_ctx *ctx, pir_status s, const char *fmt, ...) {
-  if (ctx) {
-    char buf[512];
-    va_list ap;
-    va_start(ap, fmt);
-    vsnprintf(buf, sizeof buf, fmt, ap);
-    va_end(ap);
-    ctx->err = buf;
-  }
+  char buf[512];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof buf, fmt, ap);
+  va_end(ap);
+  (ctx ? ctx->err : g_noctx_err) = buf;
   return s;
 }
 
@@ -339,23 +340,25 @@ pir_status pir_params_check(const pir_params *params, uint32_t *psi_out) {
 }
 
 pir_status pir_ctx_create(int device, size_t hbm_budget_bytes, pir_ctx **out) {
-  if (!out) return PIR_ERR_INVALID_ARG;
+  if (!out) return fail(nullptr, PIR_ERR_INVALID_ARG, "out is NULL");
   *out = nullptr;
   int n = 0;
-  if (hipGetDeviceCount(&n) != hipSuccess || device < 0 || device >= n) {
+  hipError_t e = hipGetDeviceCount(&n);
+  if (e != hipSuccess) {
     (void)hipGetLastError();
-    return PIR_ERR_DEVICE;
+    return fail(nullptr, PIR_ERR_DEVICE, "hipGetDeviceCount failed: %s", hipGetErrorString(e));
   }
+  if (device < 0 || device >= n)
+    return fail(nullptr, PIR_ERR_DEVICE, "device %d not present (%d devices)", device, n);
+  int cus = 0;
+  e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, device);
+  if (e != hipSuccess)
+    return fail(nullptr, PIR_ERR_DEVICE, "hipDeviceGetAttribute failed: %s", hipGetErrorString(e));
   pir_ctx *ctx = new (std::nothrow) pir_ctx;
-  if (!ctx) return PIR_ERR_OUT_OF_MEMORY;
+  if (!ctx) return fail(nullptr, PIR_ERR_OUT_OF_MEMORY, "host allocation failed");
   ctx->device = device;
   ctx->budget = hbm_budget_bytes;
-  hipDeviceProp_t prop;
-  if (hipGetDeviceProperties(&prop, device) != hipSuccess) {
-    delete ctx;
-    return PIR_ERR_DEVICE;
-  }
-  ctx->num_cus = prop.multiProcessorCount;
+  ctx->num_cus = cus;
   *out = ctx;
   return PIR_OK;
 }
@@ -371,7 +374,9 @@ void pir_ctx_destroy(pir_ctx *ctx) {
   delete ctx;
 }
 
-const char *pir_last_error(const pir_ctx *ctx) { return ctx ? ctx->err.c_str() : "no context"; }
+const char *pir_last_error(const pir_ctx *ctx) {
+  return ctx ? ctx->err.c_str() : g_noctx_err.c_str();
+}
 
 size_t pir_ctx_device_bytes(const pir_ctx *ctx) { return ctx ? ctx->held : 0; }
 

@@ -78,6 +78,10 @@ class PirError(RuntimeError):
 def _load() -> ct.CDLL:
     if not os.path.exists(LIB_PATH):
         raise ImportError(f"{LIB_PATH} is not built: run `python -m paper_2606_11536_amd.build`")
+    # PyTorch ships its own HIP runtime (same soname as the system one).  Load it
+    # first so libpir binds to the runtime that owns torch's device memory and
+    # streams; a second HIP/HSA runtime in the process would not see the GPU.
+    import torch  # noqa: F401
     lib = ct.CDLL(LIB_PATH)
     for name, (res, args) in SIGNATURES.items():
         fn = getattr(lib, name)
@@ -91,7 +95,7 @@ lib = _load()
 
 def _check(st: int, ctx=None) -> None:
     if st != 0:
-        msg = lib.pir_last_error(ctx).decode() if ctx else ""
+        msg = lib.pir_last_error(ctx).decode()
         raise PirError(st, msg or lib.pir_status_string(st).decode())
 
 
