@@ -136,6 +136,7 @@ def main() -> int:
     ap.add_argument("--seed", type=int, default=0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--latency-steps", type=int, default=50)
+    ap.add_argument("--no-tune", action="store_true", help="use the default scan variant")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="only run a plain 1 GiB device copy (for HBM counter scaling)")
     args = ap.parse_args()
@@ -171,6 +172,10 @@ def main() -> int:
         qc[b] = torch.from_numpy(synth.uniform_query(args.seed, b, R, primes, N).view(np.int32)).to(dev)
     ans = torch.empty((B, C, 2, K, N), dtype=torch.int32, device=dev)
     jobs = [(db, B, qc, ans)]
+    tune_report = None
+    if not args.no_tune:
+        tune_report = ctx.tune(db, B)
+        log(f"[bench] tuned scan: {tune_report}")
 
     for _ in range(args.warmup):
         ctx.answer_batch(jobs)
@@ -230,6 +235,7 @@ def main() -> int:
                        "p99": round(float(np.percentile(lat, 99)), 4),
                        "what": "one pir_answer_batch call of B queries, host clock, synchronized"},
         "stage_ms": {s: round(v[0] / max(v[1], 1), 5) for s, v in stage.items()},
+        "scan_tuning": tune_report,
         "roofline": {
             "bound": "hbm",
             "kernel": kernel,

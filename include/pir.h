@@ -178,6 +178,25 @@ typedef struct {
 pir_status pir_answer_batch(pir_ctx *ctx, const pir_job *jobs, size_t n_jobs,
                             pir_stream stream);
 
+/* ---- tuning of the scan (a3).  Several kernel variants compute the same
+ * exact result with different tile shapes, unroll depths and load policies.
+ * The context remembers one variant per (N, K, R, C, B); without a choice a
+ * fixed default is used.  Results never depend on the variant. */
+
+/* Number of scan variants for batch size B (host only). */
+uint32_t pir_scan_variants(uint32_t B);
+
+/* Use variant `index` (< pir_scan_variants(B)) for databases shaped like `db`
+ * at batch size B. */
+pir_status pir_scan_select(pir_ctx *ctx, const pir_db *db, uint32_t B, uint32_t index);
+
+/* Autotune: time every variant for `db` at batch size B on `stream` (on
+ * workspace contents; values do not affect timing), keep the fastest, and wait
+ * for the stream.  If `report` is not NULL it receives up to report_len bytes
+ * of "index:kind/jbw/unr/nt=ms;" entries and the chosen index. */
+pir_status pir_tune(pir_ctx *ctx, const pir_db *db, uint32_t B, pir_stream stream, char *report,
+                    size_t report_len);
+
 /* ---- measurement: per-stage kernel time with HIP events (off by default).
  * While enabled, pir_db_mul and pir_answer_batch bracket each stage's launch
  * with a pair of HIP events on the call's stream.  pir_profile_read waits for

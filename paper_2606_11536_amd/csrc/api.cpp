@@ -6,6 +6,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <array>
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
@@ -37,6 +38,8 @@ struct pir_ctx {
   std::vector<Rec> pending;
   double stage_ms[PIR_N_STAGES] = {};
   uint64_t stage_n[PIR_N_STAGES] = {};
+  // chosen scan variant per (N, K, R, C, B)
+  std::map<std::array<uint32_t, 5>, ScanCfg> scan_cfg;
 };
 
 struct pir_db {
@@ -293,8 +296,20 @@ void profile_drain(pir_ctx *ctx) {
 }
 
 size_t query_atom_bytes(const DbDesc &d, uint32_t B) {
+  if (B == 1) return 0;  // the batch-1 kernel reads the NTT-form query directly
   const uint32_t n_cb = (2 * B + kCB - 1) / kCB;
   return (size_t)d.K * d.N * d.n_ib * n_cb * kAtomBytes;
+}
+
+std::array<uint32_t, 5> shape_key(const DbDesc &d, uint32_t B) { return {d.N, d.K, d.R, d.C, B}; }
+
+ScanCfg chosen_cfg(const pir_ctx *ctx, const DbDesc &d, uint32_t B) {
+  auto it = ctx->scan_cfg.find(shape_key(d, B));
+  return it != ctx->scan_cfg.end() ? it->second : scan_default(B);
+}
+
+hipError_t run_scan(pir_ctx *ctx, const ScanJob &job, hipStream_t s) {
+  return launch_scan(job, chosen_cfg(ctx, job.db, job.B), s);
 }
 
 }  // namespace
@@ -534,14 +549,14 @@ pir_status pir_db_mul(pir_ctx *ctx, const pir_db *db, const uint32_t *query_ntt,
   if (st != PIR_OK) return st;
   hipStream_t s = (hipStream_t)stream;
   uint8_t *qatoms = (uint8_t *)ctx->ws;
-  {
+  if (B > 1) {
     StageTimer tm(ctx, s, PIR_STAGE_PACK);
     HIP_OR_FAIL(ctx, launch_pack_query(query_ntt, qatoms, B, db->R, db->desc.N, db->desc.K, s));
   }
-  ScanJob job{db->desc, qatoms, answer_ntt, B};
+  ScanJob job{db->desc, qatoms, query_ntt, answer_ntt, B};
   {
     StageTimer tm(ctx, s, PIR_STAGE_SCAN);
-    HIP_OR_FAIL(ctx, launch_scan(job, ctx->num_cus, s));
+    HIP_OR_FAIL(ctx, run_scan(ctx, job, s));
   }
   return PIR_OK;
 }
@@ -549,7 +564,11 @@ pir_status pir_db_mul(pir_ctx *ctx, const pir_db *db, const uint32_t *query_ntt,
 pir_status pir_answer_batch(pir_ctx *ctx, const pir_job *jobs, size_t n_jobs, pir_stream stream) {
   if (!ctx) return PIR_ERR_INVALID_ARG;
   if (!jobs && n_jobs) return fail(ctx, PIR_ERR_INVALID_ARG, "jobs is NULL");
-  size_t max_q = 0, sum_atoms = 0;
+  // Workspace: one shared region for the NTT-form queries of batched jobs
+  // (consumed by their pack before the next job's NTT), a region of its own
+  // for each batch-1 job (read by its scan), and the query atoms of every job.
+  auto al = [](size_t x) { return (x + 255) & ~(size_t)255; };
+  size_t shared_q = 0, own_q = 0, sum_atoms = 0;
   for (size_t n = 0; n < n_jobs; ++n) {
     const pir_job &j = jobs[n];
     if (!j.db || !j.query_coeff || !j.answer_coeff)
@@ -559,42 +578,117 @@ pir_status pir_answer_batch(pir_ctx *ctx, const pir_job *jobs, size_t n_jobs, pi
     if (j.B < 1 || j.B > PIR_MAX_BATCH)
       return fail(ctx, PIR_ERR_INVALID_ARG, "job %zu: B=%u out of range", n, j.B);
     const DbDesc &d = j.db->desc;
-    max_q = std::max(max_q, (size_t)j.B * d.R * 2 * d.K * d.N * 4);
-    sum_atoms += (query_atom_bytes(d, j.B) + 255) & ~(size_t)255;
+    const size_t qb = al((size_t)j.B * d.R * 2 * d.K * d.N * 4);
+    if (j.B == 1) own_q += qb;
+    else shared_q = std::max(shared_q, qb);
+    sum_atoms += al(query_atom_bytes(d, j.B));
   }
   if (n_jobs == 0) return PIR_OK;
   DeviceGuard g(ctx->device);
-  const size_t q_region = (max_q + 255) & ~(size_t)255;
-  pir_status st = ensure_ws(ctx, q_region + sum_atoms);
+  pir_status st = ensure_ws(ctx, shared_q + own_q + sum_atoms);
   if (st != PIR_OK) return st;
   hipStream_t s = (hipStream_t)stream;
-  uint32_t *qntt = (uint32_t *)ctx->ws;
-  uint8_t *atoms = (uint8_t *)ctx->ws + q_region;
+  uint8_t *base = (uint8_t *)ctx->ws;
+  uint32_t *shared = (uint32_t *)base;
+  uint8_t *own = base + shared_q;
+  uint8_t *atoms = own + own_q;
   std::vector<ScanJob> sj(n_jobs);
   for (size_t n = 0; n < n_jobs; ++n) {
     const pir_job &j = jobs[n];
     const DbDesc &d = j.db->desc;
+    uint32_t *qntt = shared;
+    if (j.B == 1) {
+      qntt = (uint32_t *)own;
+      own += al((size_t)d.R * 2 * d.K * d.N * 4);
+    }
     {
       StageTimer tm(ctx, s, PIR_STAGE_NTT);
       HIP_OR_FAIL(ctx, launch_ntt_copy(j.query_coeff, qntt, (size_t)j.B * d.R * 2 * d.K, d.K,
                                        d.log2n, d.primes, s));
     }
-    {
+    if (j.B > 1) {
       StageTimer tm(ctx, s, PIR_STAGE_PACK);
       HIP_OR_FAIL(ctx, launch_pack_query(qntt, atoms, j.B, d.R, d.N, d.K, s));
     }
-    sj[n] = ScanJob{d, atoms, j.answer_coeff, j.B};
-    atoms += (query_atom_bytes(d, j.B) + 255) & ~(size_t)255;
+    sj[n] = ScanJob{d, atoms, qntt, j.answer_coeff, j.B};
+    atoms += al(query_atom_bytes(d, j.B));
   }
   for (size_t n = 0; n < n_jobs; ++n) {
     StageTimer tm(ctx, s, PIR_STAGE_SCAN);
-    HIP_OR_FAIL(ctx, launch_scan(sj[n], ctx->num_cus, s));
+    HIP_OR_FAIL(ctx, run_scan(ctx, sj[n], s));
   }
   for (size_t n = 0; n < n_jobs; ++n) {
     const DbDesc &d = sj[n].db;
     StageTimer tm(ctx, s, PIR_STAGE_INTT);
     HIP_OR_FAIL(ctx, launch_ntt(sj[n].out, (size_t)sj[n].B * d.C * 2 * d.K, d.K, d.log2n, d.primes,
                                 true, s));
+  }
+  return PIR_OK;
+}
+
+uint32_t pir_scan_variants(uint32_t B) {
+  return (B >= 1 && B <= PIR_MAX_BATCH) ? (uint32_t)scan_candidates(B).size() : 0;
+}
+
+pir_status pir_scan_select(pir_ctx *ctx, const pir_db *db, uint32_t B, uint32_t index) {
+  if (!ctx) return PIR_ERR_INVALID_ARG;
+  if (!db || B < 1 || B > PIR_MAX_BATCH) return fail(ctx, PIR_ERR_INVALID_ARG, "bad db or B");
+  const std::vector<ScanCfg> c = scan_candidates(B);
+  if (index >= c.size()) return fail(ctx, PIR_ERR_INVALID_ARG, "variant %u out of range", index);
+  ctx->scan_cfg[shape_key(db->desc, B)] = c[index];
+  return PIR_OK;
+}
+
+pir_status pir_tune(pir_ctx *ctx, const pir_db *db, uint32_t B, pir_stream stream, char *report,
+                    size_t report_len) {
+  if (!ctx) return PIR_ERR_INVALID_ARG;
+  if (!db || B < 1 || B > PIR_MAX_BATCH) return fail(ctx, PIR_ERR_INVALID_ARG, "bad db or B");
+  if (db->ctx != ctx) return fail(ctx, PIR_ERR_INVALID_ARG, "database belongs to another context");
+  DeviceGuard g(ctx->device);
+  const DbDesc &d = db->desc;
+  auto al = [](size_t x) { return (x + 255) & ~(size_t)255; };
+  const size_t qb = al((size_t)B * d.R * 2 * d.K * d.N * 4);
+  const size_t ab = al(query_atom_bytes(d, B));
+  const size_t ob = al((size_t)B * d.C * 2 * d.K * d.N * 4);
+  pir_status st = ensure_ws(ctx, qb + ab + ob);
+  if (st != PIR_OK) return st;
+  hipStream_t s = (hipStream_t)stream;
+  uint8_t *base = (uint8_t *)ctx->ws;
+  // Timing does not depend on values; start from a defined state all the same.
+  HIP_OR_FAIL(ctx, hipMemsetAsync(base, 0, qb + ab + ob, s));
+  ScanJob job{d, base + qb, (const uint32_t *)base, (uint32_t *)(base + qb + ab), B};
+  const std::vector<ScanCfg> cands = scan_candidates(B);
+  hipEvent_t e0, e1;
+  HIP_OR_FAIL(ctx, hipEventCreate(&e0));
+  HIP_OR_FAIL(ctx, hipEventCreate(&e1));
+  std::string rep;
+  float best = 1e30f;
+  size_t best_i = 0;
+  const int reps = 3;
+  for (size_t i = 0; i < cands.size(); ++i) {
+    HIP_OR_FAIL(ctx, launch_scan(job, cands[i], s));  // warm-up
+    HIP_OR_FAIL(ctx, hipEventRecord(e0, s));
+    for (int r = 0; r < reps; ++r) HIP_OR_FAIL(ctx, launch_scan(job, cands[i], s));
+    HIP_OR_FAIL(ctx, hipEventRecord(e1, s));
+    HIP_OR_FAIL(ctx, hipEventSynchronize(e1));
+    float ms = 0.f;
+    HIP_OR_FAIL(ctx, hipEventElapsedTime(&ms, e0, e1));
+    ms /= reps;
+    char buf[96];
+    snprintf(buf, sizeof buf, "%zu:%u/%u/%u/%u=%.4f;", i, cands[i].kind, cands[i].jbw, cands[i].unr,
+             cands[i].nt, ms);
+    rep += buf;
+    if (ms < best) best = ms, best_i = i;
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  ctx->scan_cfg[shape_key(d, B)] = cands[best_i];
+  char buf[32];
+  snprintf(buf, sizeof buf, "best=%zu", best_i);
+  rep += buf;
+  if (report && report_len) {
+    std::strncpy(report, rep.c_str(), report_len - 1);
+    report[report_len - 1] = 0;
   }
   return PIR_OK;
 }

@@ -6,6 +6,8 @@
 #include <stddef.h>
 #include <stdint.h>
 
+#include <vector>
+
 #include "../../include/pir.h"
 
 namespace pir {
@@ -91,13 +93,21 @@ hipError_t launch_pack_query(const uint32_t *q_ntt, uint8_t *qatoms, uint32_t B,
 // One scan job for the scan kernels.
 struct ScanJob {
   DbDesc db;
-  const uint8_t *qatoms;   // query atoms of this job
+  const uint8_t *qatoms;   // query atoms of this job (B > 1)
+  const uint32_t *q_ntt;   // NTT-form query [1][R][2][K][N] (B == 1)
   uint32_t *out;           // answer NTT form [B][C][2][K][N]
   uint32_t B;
 };
 
-// The scan for one job: picks the batch-1 streaming kernel or the MFMA
-// batched kernel by B.
-hipError_t launch_scan(const ScanJob &job, int num_cus, hipStream_t s);
+// A scan kernel variant.  kind 0: batch-1 streaming kernel (jbw row blocks per
+// wave, unr k-blocks of loads in flight, nt = non-temporal loads); kind 1:
+// batched MFMA kernel (jbw row blocks per wave, unr = kc atoms per LDS chunk).
+struct ScanCfg {
+  uint8_t kind, jbw, unr, nt;
+};
+
+std::vector<ScanCfg> scan_candidates(uint32_t B);
+ScanCfg scan_default(uint32_t B);
+hipError_t launch_scan(const ScanJob &job, const ScanCfg &cfg, hipStream_t s);
 
 }  // namespace pir

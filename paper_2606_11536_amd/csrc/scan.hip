@@ -19,11 +19,14 @@
 // Two kernels share the database atoms:
 //  * k_scan_b1 (B = 1): bandwidth-bound streaming.  v_mfma_i32_16x16x64_i8
 //    with 4 database rows x 4 limbs per A operand and the two ciphertext
-//    components x 4 limbs (half the B columns) per B operand.  The slot's
-//    query limbs sit in LDS; database atoms stream from HBM once.
-//  * k_scan_mfma (B > 1): v_mfma_i32_32x32x32_i8 over whole atoms, each wave a
-//    tile of database rows x up to 64 query columns; query atoms are staged in
-//    LDS per chunk of the contraction and shared by the four waves.
+//    components x 4 limbs (half the B columns) per B operand.  The block
+//    splits the slot's query limbs straight from the NTT-form query into LDS;
+//    each wave streams its database atoms from HBM with UNR k-blocks of loads
+//    in flight before the first MFMA that needs them.
+//  * k_scan_mfma (B > 1): v_mfma_i32_32x32x32_i8 over whole atoms.  A wave
+//    owns JBW x 8 database rows and up to 64 query columns; query atoms are
+//    staged in double-buffered LDS chunks of KC atoms per column block while
+//    the next chunk's database atoms are already in flight.
 #include "device_util.h"
 #include "pir_internal.h"
 
@@ -33,12 +36,12 @@ namespace {
 typedef int v4i __attribute__((ext_vector_type(4)));
 typedef int v16i __attribute__((ext_vector_type(16)));
 
-constexpr uint32_t kB1Chunk = 64;  // query ibs staged per LDS chunk (16 KiB)
+constexpr uint32_t kB1Chunk = 64;  // query ibs split into LDS per chunk (16 KiB)
 
 struct B1Args {
   DbDesc db;
-  const uint8_t *qatoms;
-  uint32_t *out;
+  const uint32_t *q;  // NTT-form query [1][R][2][K][N]
+  uint32_t *out;      // answer [1][C][2][K][N]
   uint32_t n_slots;   // K * N
   uint32_t jpb;       // jbs per block
   uint32_t total;     // logical blocks
@@ -54,9 +57,19 @@ __device__ __forceinline__ uint32_t quad_sum_mod(uint32_t s, uint32_t q) {
   return csub(s, q);
 }
 
-template <int JBW>
+template <bool NT>
+__device__ __forceinline__ v4i load_atom16(const uint8_t *p) {
+  const v4i *v = reinterpret_cast<const v4i *>(p);
+  if constexpr (NT) {
+    return __builtin_nontemporal_load(v);
+  } else {
+    return *v;
+  }
+}
+
+template <int JBW, int UNR, bool NT>
 __global__ __launch_bounds__(256) void k_scan_b1(const B1Args a) {
-  __shared__ uint4 sq[kB1Chunk * 16];
+  __shared__ uint32_t sq[kB1Chunk * 64];
   const uint32_t L = xcd_logical(blockIdx.x, gridDim.x);
   if (L >= a.total) return;
   const DbDesc &db = a.db;
@@ -72,7 +85,10 @@ __global__ __launch_bounds__(256) void k_scan_b1(const B1Args a) {
   const uint32_t jb_end = min(jb_begin + a.jpb, n_jb);
   const uint8_t *slot_atoms = db.atoms + (size_t)slot * n_jb * n_ib * kAtomBytes;
   const uint32_t lane_off = (g >> 1) * 1024 + (g & 1) * 512 + m * 16;
-  const uint4 *qsrc = reinterpret_cast<const uint4 *>(a.qatoms) + (size_t)slot * n_ib * 64;
+  const bool bzero = m >= 8;
+  const size_t qrow = (size_t)db.K * db.N;  // stride between (i, c) rows of the query
+  const uint32_t *qbase = a.q + (size_t)k * db.N + t;
+  const uint4 *sq4 = reinterpret_cast<const uint4 *>(sq);
 
   v4i acc[JBW][2];
 #pragma unroll
@@ -81,9 +97,24 @@ __global__ __launch_bounds__(256) void k_scan_b1(const B1Args a) {
   for (uint32_t ib0 = 0; ib0 < n_ib; ib0 += kB1Chunk) {
     const uint32_t nib = min(kB1Chunk, n_ib - ib0);  // even: R_pad is a multiple of 64
     __syncthreads();
+    // Split the slot's query residues into limb bytes: item (ibl, half, c, e4)
+    // covers i = 32 (ib0+ibl) + 16 half + 4 e4 + u, u < 4, and writes one word
+    // per limb b at LDS lane (half, 4c + b), bytes 4 e4 .. 4 e4 + 3.
     for (uint32_t idx = tid; idx < nib * 16; idx += 256) {
       const uint32_t ibl = idx >> 4, r = idx & 15;
-      sq[idx] = qsrc[(size_t)(ib0 + ibl) * 64 + (r >> 3) * 32 + (r & 7)];
+      const uint32_t half = r >> 3, c = (r >> 2) & 1, e4 = r & 3;
+      const uint32_t i0 = (ib0 + ibl) * 32 + half * 16 + e4 * 4;
+      uint32_t v[4];
+#pragma unroll
+      for (int u = 0; u < 4; ++u)
+        v[u] = (i0 + u < db.R) ? qbase[((size_t)(i0 + u) * 2 + c) * qrow] : 0u;
+#pragma unroll
+      for (uint32_t b = 0; b < 4; ++b) {
+        uint32_t w = 0;
+#pragma unroll
+        for (int u = 0; u < 4; ++u) w |= ((v[u] >> (7 * b)) & 127u) << (8 * u);
+        sq[((ibl * 2 + half) * 8 + c * 4 + b) * 4 + e4] = w;
+      }
     }
     __syncthreads();
     const uint32_t nkb = nib >> 1;
@@ -92,17 +123,29 @@ __global__ __launch_bounds__(256) void k_scan_b1(const B1Args a) {
       const uint32_t jb = jb_begin + wave + 4 * w;
       if (jb >= jb_end) break;
       const uint8_t *base = slot_atoms + ((size_t)jb * n_ib + ib0) * kAtomBytes + lane_off;
-#pragma unroll 4
-      for (uint32_t kb = 0; kb < nkb; ++kb) {
-        const v4i a0 = *reinterpret_cast<const v4i *>(base + (size_t)kb * 2048);
-        const v4i a1 = *reinterpret_cast<const v4i *>(base + (size_t)kb * 2048 + 256);
-        v4i bv = v4i{0, 0, 0, 0};
-        if (m < 8) {
-          const uint4 u = sq[(2 * kb + (g >> 1)) * 16 + (g & 1) * 8 + m];
-          bv = v4i{(int)u.x, (int)u.y, (int)u.z, (int)u.w};
+      auto mma = [&](const v4i &x0, const v4i &x1, uint32_t kb) {
+        // every lane reads a valid address; lanes of the empty columns 8..15 then zero it
+        const uint4 x = sq4[(2 * kb + (g >> 1)) * 16 + (g & 1) * 8 + (m & 7)];
+        const v4i bv = bzero ? v4i{0, 0, 0, 0} : v4i{(int)x.x, (int)x.y, (int)x.z, (int)x.w};
+        acc[w][0] = __builtin_amdgcn_mfma_i32_16x16x64_i8(x0, bv, acc[w][0], 0, 0, 0);
+        acc[w][1] = __builtin_amdgcn_mfma_i32_16x16x64_i8(x1, bv, acc[w][1], 0, 0, 0);
+      };
+      uint32_t kb0 = 0;
+      // full groups: UNR k-blocks of loads issued before the first of their MFMAs
+      for (; kb0 + UNR <= nkb; kb0 += UNR) {
+        v4i a0[UNR], a1[UNR];
+#pragma unroll
+        for (int u = 0; u < UNR; ++u) {
+          a0[u] = load_atom16<NT>(base + (size_t)(kb0 + u) * 2048);
+          a1[u] = load_atom16<NT>(base + (size_t)(kb0 + u) * 2048 + 256);
         }
-        acc[w][0] = __builtin_amdgcn_mfma_i32_16x16x64_i8(a0, bv, acc[w][0], 0, 0, 0);
-        acc[w][1] = __builtin_amdgcn_mfma_i32_16x16x64_i8(a1, bv, acc[w][1], 0, 0, 0);
+#pragma unroll
+        for (int u = 0; u < UNR; ++u) mma(a0[u], a1[u], kb0 + u);
+      }
+      for (; kb0 < nkb; ++kb0) {
+        const v4i x0 = load_atom16<NT>(base + (size_t)kb0 * 2048);
+        const v4i x1 = load_atom16<NT>(base + (size_t)kb0 * 2048 + 256);
+        mma(x0, x1, kb0);
       }
     }
   }
@@ -136,7 +179,6 @@ __global__ __launch_bounds__(256) void k_scan_b1(const B1Args a) {
 }
 
 // ---------------------------------------------------------------------------
-constexpr uint32_t kKC = 4;   // query ibs per LDS chunk
 constexpr uint32_t kCBT = 8;  // query atoms (8 columns each) per block tile
 
 struct MfArgs {
@@ -148,9 +190,11 @@ struct MfArgs {
   uint32_t total;
 };
 
-template <int JBW>
+template <int JBW, int KC>
 __global__ __launch_bounds__(256) void k_scan_mfma(const MfArgs a) {
-  __shared__ uint4 sq[kKC * kCBT * 64];  // 32 KiB
+  constexpr uint32_t kBuf = KC * kCBT * 64;  // uint4 per LDS buffer
+  constexpr uint32_t kPer = kBuf / 256;      // staged uint4 per thread
+  __shared__ uint4 sq[2 * kBuf];
   const uint32_t L = xcd_logical(blockIdx.x, gridDim.x);
   if (L >= a.total) return;
   const DbDesc &db = a.db;
@@ -161,19 +205,41 @@ __global__ __launch_bounds__(256) void k_scan_mfma(const MfArgs a) {
   const DevPrime &P = db.primes[k];
   const uint32_t q = P.q;
   const uint32_t tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
-  const uint32_t n_ib = db.n_ib, n_jb = db.n_jb;
+  const uint32_t n_ib = db.n_ib, n_jb = db.n_jb, n_cb = a.n_cb;
   const uint32_t cb0 = cbt * kCBT;
-  const uint32_t ncb = min(kCBT, a.n_cb - cb0);
+  const uint32_t ncb = min(kCBT, n_cb - cb0);
 
   uint32_t jbs[JBW];
   bool jv[JBW];
+  const uint8_t *arow[JBW];
+  const uint8_t *slot_atoms = db.atoms + (size_t)slot * n_jb * n_ib * kAtomBytes + lane * 16;
 #pragma unroll
   for (int w = 0; w < JBW; ++w) {
     jbs[w] = (jg * 4 + wave) * JBW + w;
     jv[w] = jbs[w] < n_jb;
+    arow[w] = slot_atoms + (size_t)(jv[w] ? jbs[w] : 0) * n_ib * kAtomBytes;
   }
-  const uint8_t *slot_atoms = db.atoms + (size_t)slot * n_jb * n_ib * kAtomBytes + lane * 16;
-  const uint4 *qsrc = reinterpret_cast<const uint4 *>(a.qatoms) + (size_t)slot * n_ib * a.n_cb * 64;
+  const uint4 *qsrc = reinterpret_cast<const uint4 *>(a.qatoms) + (size_t)slot * n_ib * n_cb * 64;
+
+  auto stage_load = [&](uint32_t ib0, uint4 (&st)[kPer]) {
+#pragma unroll
+    for (uint32_t r = 0; r < kPer; ++r) {
+      const uint32_t idx = tid + 256 * r;
+      const uint32_t kk = idx / (kCBT * 64), c = (idx / 64) % kCBT, l = idx & 63;
+      st[r] = make_uint4(0, 0, 0, 0);
+      if (ib0 + kk < n_ib && c < ncb) st[r] = qsrc[((size_t)(ib0 + kk) * n_cb + cb0 + c) * 64 + l];
+    }
+  };
+  auto a_load = [&](uint32_t ib0, v4i (&av)[JBW][KC]) {
+#pragma unroll
+    for (int w = 0; w < JBW; ++w)
+#pragma unroll
+      for (int kk = 0; kk < KC; ++kk) {
+        av[w][kk] = v4i{0, 0, 0, 0};
+        if (jv[w] && ib0 + kk < n_ib)
+          av[w][kk] = *reinterpret_cast<const v4i *>(arow[w] + (size_t)(ib0 + kk) * kAtomBytes);
+      }
+  };
 
   v16i acc[JBW][kCBT];
 #pragma unroll
@@ -181,35 +247,46 @@ __global__ __launch_bounds__(256) void k_scan_mfma(const MfArgs a) {
 #pragma unroll
     for (int c = 0; c < (int)kCBT; ++c) acc[w][c] = v16i{};
 
-  for (uint32_t ib0 = 0; ib0 < n_ib; ib0 += kKC) {
-    const uint32_t nib = min(kKC, n_ib - ib0);
-    __syncthreads();
-    for (uint32_t idx = tid; idx < kKC * kCBT * 64; idx += 256) {
-      const uint32_t kk = idx / (kCBT * 64), c = (idx / 64) % kCBT, l = idx & 63;
-      uint4 v = make_uint4(0, 0, 0, 0);
-      if (kk < nib && c < ncb) v = qsrc[((size_t)(ib0 + kk) * a.n_cb + cb0 + c) * 64 + l];
-      sq[idx] = v;
-    }
-    __syncthreads();
-    for (uint32_t kk = 0; kk < nib; ++kk) {
-      v4i av[JBW];
+  const uint32_t n_chunks = (n_ib + KC - 1) / KC;
+  uint4 st[kPer];
+  v4i acur[JBW][KC], anext[JBW][KC];
+  stage_load(0, st);
 #pragma unroll
-      for (int w = 0; w < JBW; ++w) {
-        av[w] = v4i{0, 0, 0, 0};
-        if (jv[w])
-          av[w] = *reinterpret_cast<const v4i *>(slot_atoms +
-                                                 ((size_t)jbs[w] * n_ib + ib0 + kk) * kAtomBytes);
-      }
+  for (uint32_t r = 0; r < kPer; ++r) sq[tid + 256 * r] = st[r];
+  a_load(0, acur);
+  __syncthreads();
+
+  for (uint32_t ch = 0; ch < n_chunks; ++ch) {
+    const uint32_t ib0 = ch * KC;
+    const bool more = ch + 1 < n_chunks;
+    if (more) {
+      stage_load(ib0 + KC, st);
+      a_load(ib0 + KC, anext);
+    }
+    const uint4 *buf = sq + (ch & 1) * kBuf;
+#pragma unroll
+    for (int kk = 0; kk < KC; ++kk) {
+      if (ib0 + kk >= n_ib) break;
 #pragma unroll
       for (int c = 0; c < (int)kCBT; ++c) {
         if ((uint32_t)c >= ncb) break;
-        const uint4 u = sq[(kk * kCBT + c) * 64 + lane];
+        const uint4 u = buf[(kk * kCBT + c) * 64 + lane];
         const v4i bv = v4i{(int)u.x, (int)u.y, (int)u.z, (int)u.w};
 #pragma unroll
         for (int w = 0; w < JBW; ++w)
-          acc[w][c] = __builtin_amdgcn_mfma_i32_32x32x32_i8(av[w], bv, acc[w][c], 0, 0, 0);
+          acc[w][c] = __builtin_amdgcn_mfma_i32_32x32x32_i8(acur[w][kk], bv, acc[w][c], 0, 0, 0);
       }
     }
+    if (more) {
+      uint4 *nb = sq + ((ch + 1) & 1) * kBuf;
+#pragma unroll
+      for (uint32_t r = 0; r < kPer; ++r) nb[tid + 256 * r] = st[r];
+#pragma unroll
+      for (int w = 0; w < JBW; ++w)
+#pragma unroll
+        for (int kk = 0; kk < KC; ++kk) acur[w][kk] = anext[w][kk];
+    }
+    __syncthreads();
   }
 
   // Epilogue.  32x32 result: lane holds column lane & 31 (= 4 cc + b) and, in
@@ -249,38 +326,75 @@ __global__ __launch_bounds__(256) void k_scan_mfma(const MfArgs a) {
 
 inline uint32_t round8(uint32_t x) { return (x + 7) / 8 * 8; }
 
-}  // namespace
-
-hipError_t launch_scan(const ScanJob &job, int num_cus, hipStream_t s) {
-  (void)num_cus;
+template <int JBW, int UNR, bool NT>
+hipError_t run_b1(const ScanJob &job, hipStream_t s) {
   const DbDesc &db = job.db;
-  const uint32_t n_slots = db.K * db.N;
-  if (job.B == 1) {
-    constexpr int JBW = 8;
-    B1Args a;
-    a.db = db;
-    a.qatoms = job.qatoms;
-    a.out = job.out;
-    a.n_slots = n_slots;
-    a.jpb = 4 * JBW;
-    const uint32_t n_jchunks = (db.n_jb + a.jpb - 1) / a.jpb;
-    a.total = n_slots * n_jchunks;
-    k_scan_b1<JBW><<<round8(a.total), 256, 0, s>>>(a);
-    return hipGetLastError();
-  }
-  constexpr int JBW = 1;
+  B1Args a;
+  a.db = db;
+  a.q = job.q_ntt;
+  a.out = job.out;
+  a.n_slots = db.K * db.N;
+  a.jpb = 4 * JBW;
+  const uint32_t n_jchunks = (db.n_jb + a.jpb - 1) / a.jpb;
+  a.total = a.n_slots * n_jchunks;
+  k_scan_b1<JBW, UNR, NT><<<round8(a.total), 256, 0, s>>>(a);
+  return hipGetLastError();
+}
+
+template <int JBW, int KC>
+hipError_t run_mfma(const ScanJob &job, hipStream_t s) {
+  const DbDesc &db = job.db;
   MfArgs a;
   a.db = db;
   a.qatoms = job.qatoms;
   a.out = job.out;
   a.B = job.B;
   a.n_cb = (2 * job.B + kCB - 1) / kCB;
-  a.n_slots = n_slots;
+  a.n_slots = db.K * db.N;
   a.n_jg = (db.n_jb + 4 * JBW - 1) / (4 * JBW);
   a.n_cbt = (a.n_cb + kCBT - 1) / kCBT;
-  a.total = a.n_cbt * n_slots * a.n_jg;
-  k_scan_mfma<JBW><<<round8(a.total), 256, 0, s>>>(a);
+  a.total = a.n_cbt * a.n_slots * a.n_jg;
+  k_scan_mfma<JBW, KC><<<round8(a.total), 256, 0, s>>>(a);
   return hipGetLastError();
+}
+
+typedef hipError_t (*ScanFn)(const ScanJob &, hipStream_t);
+
+struct Variant {
+  ScanCfg cfg;
+  ScanFn fn;
+};
+
+const Variant kVariants[] = {
+    // batch-1 streaming: (kind 0, jbw, unroll, nontemporal)
+    {{0, 8, 4, 0}, run_b1<8, 4, false>}, {{0, 8, 8, 0}, run_b1<8, 8, false>},
+    {{0, 4, 4, 0}, run_b1<4, 4, false>}, {{0, 4, 8, 0}, run_b1<4, 8, false>},
+    {{0, 2, 8, 0}, run_b1<2, 8, false>}, {{0, 8, 4, 1}, run_b1<8, 4, true>},
+    {{0, 4, 8, 1}, run_b1<4, 8, true>},  {{0, 2, 8, 1}, run_b1<2, 8, true>},
+    // batched MFMA: (kind 1, jbw, kc, -)
+    {{1, 1, 2, 0}, run_mfma<1, 2>},      {{1, 1, 4, 0}, run_mfma<1, 4>},
+    {{1, 2, 2, 0}, run_mfma<2, 2>},
+};
+
+}  // namespace
+
+std::vector<ScanCfg> scan_candidates(uint32_t B) {
+  std::vector<ScanCfg> out;
+  for (const Variant &v : kVariants)
+    if ((v.cfg.kind == 0) == (B == 1)) out.push_back(v.cfg);
+  return out;
+}
+
+ScanCfg scan_default(uint32_t B) {
+  return B == 1 ? ScanCfg{0, 4, 8, 0} : ScanCfg{1, 1, 4, 0};
+}
+
+hipError_t launch_scan(const ScanJob &job, const ScanCfg &cfg, hipStream_t s) {
+  if ((cfg.kind == 0) != (job.B == 1)) return hipErrorInvalidValue;
+  for (const Variant &v : kVariants)
+    if (v.cfg.kind == cfg.kind && v.cfg.jbw == cfg.jbw && v.cfg.unr == cfg.unr && v.cfg.nt == cfg.nt)
+      return v.fn(job, s);
+  return hipErrorInvalidValue;
 }
 
 }  // namespace pir

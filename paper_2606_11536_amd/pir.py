@@ -61,6 +61,9 @@ SIGNATURES = {
     "pir_intt": (ct.c_int, [_P, ct.POINTER(CParams), _P, ct.c_size_t, _P]),
     "pir_db_mul": (ct.c_int, [_P, _P, _P, _U32, _P, _P]),
     "pir_answer_batch": (ct.c_int, [_P, ct.POINTER(CJob), ct.c_size_t, _P]),
+    "pir_scan_variants": (ct.c_uint32, [_U32]),
+    "pir_scan_select": (ct.c_int, [_P, _P, _U32, _U32]),
+    "pir_tune": (ct.c_int, [_P, _P, _U32, _P, ct.c_char_p, ct.c_size_t]),
     "pir_profile_enable": (ct.c_int, [_P, ct.c_int]),
     "pir_profile_read": (ct.c_int, [_P, _U32, ct.POINTER(ct.c_double),
                                     ct.POINTER(ct.c_uint64)]),
@@ -271,3 +274,18 @@ class Context:
         _check(lib.pir_profile_read(self.handle, STAGES[stage], ct.byref(ms), ct.byref(n)),
                self.handle)
         return ms.value, n.value
+
+    def scan_select(self, db: Database, B: int, index: int) -> None:
+        """Use scan variant `index` for databases shaped like `db` at batch size B."""
+        _check(lib.pir_scan_select(self.handle, db.handle, B, index), self.handle)
+
+    def tune(self, db: Database, B: int, stream=None) -> str:
+        """Time every scan variant for (db, B), keep the fastest; returns the report."""
+        buf = ct.create_string_buffer(4096)
+        _check(lib.pir_tune(self.handle, db.handle, B, _stream(stream), buf, len(buf)),
+               self.handle)
+        return buf.value.decode()
+
+
+def scan_variants(B: int) -> int:
+    return lib.pir_scan_variants(B)

@@ -181,3 +181,28 @@ def test_batch1_full_size(ctx):
     m, noise = oq.decrypt_answers(ans[0], s[0], rg.primes, rg.psis, rg.delta, rg.p)
     assert np.array_equal(m, raw[i_star].astype(np.int64))
     assert max(abs(int(v)) for v in noise.ravel()) < rg.delta // 2
+
+
+@pytest.mark.parametrize("log2n,K,R,C,B", [(10, 2, 200, 45, 1), (11, 1, 130, 300, 1),
+                                           (10, 2, 200, 45, 3), (10, 1, 97, 70, 17)])
+def test_every_scan_variant_matches_oracle(ctx, log2n, K, R, C, B):
+    from paper_2606_11536_amd import pir
+    rg = ring(log2n, K)
+    raw = synth.db_bytes(7 * R + C, R, C, rg.N)
+    rng = np.random.default_rng(R + 3 * C + B)
+    q_hat = residues(rng, (B, R, 2), rg)
+    db = ctx.load_db(rg.pir_params(), raw, R, C)
+    exp = osc.db_mul(osc.db_ntt(raw, rg.primes, rg.psis), q_hat, rg.primes)
+    qd = to_dev(q_hat)
+    n = pir.scan_variants(B)
+    assert n >= 2
+    for v in range(n):
+        ctx.scan_select(db, B, v)
+        out = empty_dev((B, C, 2, K, rg.N))
+        ctx.db_mul(db, qd, B, out)
+        assert np.array_equal(to_host(out), exp), f"variant {v}"
+    report = ctx.tune(db, B)
+    assert "best=" in report
+    out = empty_dev((B, C, 2, K, rg.N))
+    ctx.db_mul(db, qd, B, out)
+    assert np.array_equal(to_host(out), exp)
