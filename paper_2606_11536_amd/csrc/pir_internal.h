@@ -101,7 +101,8 @@ struct ScanJob {
 
 // A scan kernel variant.  kind 0: batch-1 streaming kernel (jbw row blocks per
 // wave, unr k-blocks of loads in flight, nt = non-temporal loads); kind 1:
-// batched MFMA kernel (jbw row blocks per wave, unr = kc atoms per LDS chunk).
+// batched MFMA kernel (jbw row blocks per wave, unr = database-atom ring
+// depth, nt = log2 of the query column blocks per wave).
 struct ScanCfg {
   uint8_t kind, jbw, unr, nt;
 };

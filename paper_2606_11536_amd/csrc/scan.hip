@@ -24,9 +24,9 @@
 //    each wave streams its database atoms from HBM with UNR k-blocks of loads
 //    in flight before the first MFMA that needs them.
 //  * k_scan_mfma (B > 1): v_mfma_i32_32x32x32_i8 over whole atoms.  A wave
-//    owns JBW x 8 database rows and up to 64 query columns; query atoms are
-//    staged in double-buffered LDS chunks of KC atoms per column block while
-//    the next chunk's database atoms are already in flight.
+//    owns JBW x 8 database rows and CBW x 8 query columns; database atoms come
+//    through a register ring D contraction steps deep, query atoms through
+//    double-buffered LDS chunks shared by the block's four waves.
 #include "device_util.h"
 #include "pir_internal.h"
 
@@ -179,7 +179,7 @@ __global__ __launch_bounds__(256) void k_scan_b1(const B1Args a) {
 }
 
 // ---------------------------------------------------------------------------
-constexpr uint32_t kCBT = 8;  // query atoms (8 columns each) per block tile
+constexpr uint32_t kKCB = 4;  // contraction atoms per staged query chunk
 
 struct MfArgs {
   DbDesc db;
@@ -190,10 +190,16 @@ struct MfArgs {
   uint32_t total;
 };
 
-template <int JBW, int KC>
+// JBW database row blocks x CBW query column blocks per wave; the four waves of
+// a block take consecutive row blocks.  D = depth of the database-atom ring:
+// the atoms of contraction step ks + D are requested while step ks computes.
+// Steps past the end read a clamped (valid) atom and meet zero query atoms, so
+// the loop has no data-dependent branch and the load counters stay exact.
+template <int JBW, int CBW, int D>
 __global__ __launch_bounds__(256) void k_scan_mfma(const MfArgs a) {
-  constexpr uint32_t kBuf = KC * kCBT * 64;  // uint4 per LDS buffer
-  constexpr uint32_t kPer = kBuf / 256;      // staged uint4 per thread
+  static_assert(D % kKCB == 0, "ring depth must be a multiple of the query chunk");
+  constexpr uint32_t kBuf = kKCB * CBW * 64;  // uint4 per LDS buffer
+  constexpr uint32_t kPer = (kBuf + 255) / 256;
   __shared__ uint4 sq[2 * kBuf];
   const uint32_t L = xcd_logical(blockIdx.x, gridDim.x);
   if (L >= a.total) return;
@@ -206,8 +212,8 @@ __global__ __launch_bounds__(256) void k_scan_mfma(const MfArgs a) {
   const uint32_t q = P.q;
   const uint32_t tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
   const uint32_t n_ib = db.n_ib, n_jb = db.n_jb, n_cb = a.n_cb;
-  const uint32_t cb0 = cbt * kCBT;
-  const uint32_t ncb = min(kCBT, n_cb - cb0);
+  const uint32_t cb0 = cbt * CBW;
+  const uint32_t ncb = min((uint32_t)CBW, n_cb - cb0);
 
   uint32_t jbs[JBW];
   bool jv[JBW];
@@ -217,76 +223,70 @@ __global__ __launch_bounds__(256) void k_scan_mfma(const MfArgs a) {
   for (int w = 0; w < JBW; ++w) {
     jbs[w] = (jg * 4 + wave) * JBW + w;
     jv[w] = jbs[w] < n_jb;
+    // rows past C read row block 0: valid memory, results discarded
     arow[w] = slot_atoms + (size_t)(jv[w] ? jbs[w] : 0) * n_ib * kAtomBytes;
   }
   const uint4 *qsrc = reinterpret_cast<const uint4 *>(a.qatoms) + (size_t)slot * n_ib * n_cb * 64;
-
-  auto stage_load = [&](uint32_t ib0, uint4 (&st)[kPer]) {
+  const uint32_t last = n_ib - 1;
+  auto a_load = [&](int w, uint32_t ks) {
+    return __builtin_nontemporal_load(
+        reinterpret_cast<const v4i *>(arow[w] + (size_t)min(ks, last) * kAtomBytes));
+  };
+  auto stage_load = [&](uint32_t ks0, uint4 (&st)[kPer]) {
 #pragma unroll
     for (uint32_t r = 0; r < kPer; ++r) {
       const uint32_t idx = tid + 256 * r;
-      const uint32_t kk = idx / (kCBT * 64), c = (idx / 64) % kCBT, l = idx & 63;
+      const uint32_t kk = idx / (CBW * 64), c = (idx / 64) % CBW, l = idx & 63;
       st[r] = make_uint4(0, 0, 0, 0);
-      if (ib0 + kk < n_ib && c < ncb) st[r] = qsrc[((size_t)(ib0 + kk) * n_cb + cb0 + c) * 64 + l];
+      if (idx < kBuf && ks0 + kk < n_ib && c < ncb)
+        st[r] = qsrc[((size_t)(ks0 + kk) * n_cb + cb0 + c) * 64 + l];
     }
   };
-  auto a_load = [&](uint32_t ib0, v4i (&av)[JBW][KC]) {
+  auto stage_store = [&](uint4 *buf, const uint4 (&st)[kPer]) {
 #pragma unroll
-    for (int w = 0; w < JBW; ++w)
-#pragma unroll
-      for (int kk = 0; kk < KC; ++kk) {
-        av[w][kk] = v4i{0, 0, 0, 0};
-        if (jv[w] && ib0 + kk < n_ib)
-          av[w][kk] = *reinterpret_cast<const v4i *>(arow[w] + (size_t)(ib0 + kk) * kAtomBytes);
-      }
+    for (uint32_t r = 0; r < kPer; ++r)
+      if (tid + 256 * r < kBuf) buf[tid + 256 * r] = st[r];
   };
 
-  v16i acc[JBW][kCBT];
+  v16i acc[JBW][CBW];
 #pragma unroll
   for (int w = 0; w < JBW; ++w)
 #pragma unroll
-    for (int c = 0; c < (int)kCBT; ++c) acc[w][c] = v16i{};
+    for (int c = 0; c < CBW; ++c) acc[w][c] = v16i{};
 
-  const uint32_t n_chunks = (n_ib + KC - 1) / KC;
-  uint4 st[kPer];
-  v4i acur[JBW][KC], anext[JBW][KC];
-  stage_load(0, st);
+  v4i ring[D][JBW];
 #pragma unroll
-  for (uint32_t r = 0; r < kPer; ++r) sq[tid + 256 * r] = st[r];
-  a_load(0, acur);
+  for (int d = 0; d < D; ++d)
+#pragma unroll
+    for (int w = 0; w < JBW; ++w) ring[d][w] = a_load(w, d);
+  uint4 st[kPer];
+  stage_load(0, st);
+  stage_store(sq, st);
   __syncthreads();
 
-  for (uint32_t ch = 0; ch < n_chunks; ++ch) {
-    const uint32_t ib0 = ch * KC;
-    const bool more = ch + 1 < n_chunks;
-    if (more) {
-      stage_load(ib0 + KC, st);
-      a_load(ib0 + KC, anext);
-    }
-    const uint4 *buf = sq + (ch & 1) * kBuf;
+  const uint32_t n_steps = (n_ib + D - 1) / D * D;
+  for (uint32_t ks0 = 0; ks0 < n_steps; ks0 += D) {
 #pragma unroll
-    for (int kk = 0; kk < KC; ++kk) {
-      if (ib0 + kk >= n_ib) break;
+    for (int d = 0; d < D; ++d) {
+      const uint32_t ks = ks0 + d;
+      const uint32_t chunk = ks / kKCB;
+      if (d % kKCB == 0) stage_load(ks + kKCB, st);  // next chunk, in flight during this one
+      const uint4 *buf = sq + (chunk & 1) * kBuf + (d % kKCB) * CBW * 64;
 #pragma unroll
-      for (int c = 0; c < (int)kCBT; ++c) {
-        if ((uint32_t)c >= ncb) break;
-        const uint4 u = buf[(kk * kCBT + c) * 64 + lane];
+      for (int c = 0; c < CBW; ++c) {
+        const uint4 u = buf[c * 64 + lane];
         const v4i bv = v4i{(int)u.x, (int)u.y, (int)u.z, (int)u.w};
 #pragma unroll
         for (int w = 0; w < JBW; ++w)
-          acc[w][c] = __builtin_amdgcn_mfma_i32_32x32x32_i8(acur[w][kk], bv, acc[w][c], 0, 0, 0);
+          acc[w][c] = __builtin_amdgcn_mfma_i32_32x32x32_i8(ring[d][w], bv, acc[w][c], 0, 0, 0);
+      }
+#pragma unroll
+      for (int w = 0; w < JBW; ++w) ring[d][w] = a_load(w, ks + D);
+      if (d % kKCB == kKCB - 1) {
+        stage_store(sq + ((chunk + 1) & 1) * kBuf, st);
+        __syncthreads();
       }
     }
-    if (more) {
-      uint4 *nb = sq + ((ch + 1) & 1) * kBuf;
-#pragma unroll
-      for (uint32_t r = 0; r < kPer; ++r) nb[tid + 256 * r] = st[r];
-#pragma unroll
-      for (int w = 0; w < JBW; ++w)
-#pragma unroll
-        for (int kk = 0; kk < KC; ++kk) acur[w][kk] = anext[w][kk];
-    }
-    __syncthreads();
   }
 
   // Epilogue.  32x32 result: lane holds column lane & 31 (= 4 cc + b) and, in
@@ -304,7 +304,7 @@ __global__ __launch_bounds__(256) void k_scan_mfma(const MfArgs a) {
   for (int w = 0; w < JBW; ++w) {
     if (!jv[w]) continue;
 #pragma unroll
-    for (int c = 0; c < (int)kCBT; ++c) {
+    for (int c = 0; c < CBW; ++c) {
       if ((uint32_t)c >= ncb) break;
       const uint32_t col = (cb0 + c) * 8 + cc;
 #pragma unroll
@@ -341,7 +341,7 @@ hipError_t run_b1(const ScanJob &job, hipStream_t s) {
   return hipGetLastError();
 }
 
-template <int JBW, int KC>
+template <int JBW, int CBW, int D>
 hipError_t run_mfma(const ScanJob &job, hipStream_t s) {
   const DbDesc &db = job.db;
   MfArgs a;
@@ -352,9 +352,9 @@ hipError_t run_mfma(const ScanJob &job, hipStream_t s) {
   a.n_cb = (2 * job.B + kCB - 1) / kCB;
   a.n_slots = db.K * db.N;
   a.n_jg = (db.n_jb + 4 * JBW - 1) / (4 * JBW);
-  a.n_cbt = (a.n_cb + kCBT - 1) / kCBT;
+  a.n_cbt = (a.n_cb + CBW - 1) / CBW;
   a.total = a.n_cbt * a.n_slots * a.n_jg;
-  k_scan_mfma<JBW, KC><<<round8(a.total), 256, 0, s>>>(a);
+  k_scan_mfma<JBW, CBW, D><<<round8(a.total), 256, 0, s>>>(a);
   return hipGetLastError();
 }
 
@@ -365,28 +365,45 @@ struct Variant {
   ScanFn fn;
 };
 
+// ScanCfg for kind 1: jbw, unr = ring depth D, nt = log2(CBW).
+#define MF(J, C, D) {{1, J, D, C == 8 ? 3 : C == 4 ? 2 : C == 2 ? 1 : 0}, run_mfma<J, C, D>}
 const Variant kVariants[] = {
     // batch-1 streaming: (kind 0, jbw, unroll, nontemporal)
     {{0, 8, 4, 0}, run_b1<8, 4, false>}, {{0, 8, 8, 0}, run_b1<8, 8, false>},
     {{0, 4, 4, 0}, run_b1<4, 4, false>}, {{0, 4, 8, 0}, run_b1<4, 8, false>},
     {{0, 2, 8, 0}, run_b1<2, 8, false>}, {{0, 8, 4, 1}, run_b1<8, 4, true>},
     {{0, 4, 8, 1}, run_b1<4, 8, true>},  {{0, 2, 8, 1}, run_b1<2, 8, true>},
-    // batched MFMA: (kind 1, jbw, kc, -)
-    {{1, 1, 2, 0}, run_mfma<1, 2>},      {{1, 1, 4, 0}, run_mfma<1, 4>},
-    {{1, 2, 2, 0}, run_mfma<2, 2>},
+    // batched MFMA
+    MF(1, 1, 8), MF(2, 1, 8), MF(4, 1, 8),
+    MF(1, 2, 8), MF(2, 2, 8), MF(4, 2, 8),
+    MF(1, 4, 8), MF(2, 4, 8), MF(2, 4, 4),
+    MF(1, 8, 8), MF(2, 8, 8), MF(2, 8, 4), MF(1, 8, 4),
 };
+#undef MF
+
+// Column blocks per wave worth trying for a batch of B queries.
+uint32_t cbw_for(uint32_t B) {
+  const uint32_t n_cb = (2 * B + kCB - 1) / kCB;
+  return n_cb >= 8 ? 8 : n_cb >= 4 ? 4 : n_cb >= 2 ? 2 : 1;
+}
 
 }  // namespace
 
 std::vector<ScanCfg> scan_candidates(uint32_t B) {
   std::vector<ScanCfg> out;
-  for (const Variant &v : kVariants)
-    if ((v.cfg.kind == 0) == (B == 1)) out.push_back(v.cfg);
+  const uint32_t cbw = cbw_for(B);
+  for (const Variant &v : kVariants) {
+    if (B == 1 ? v.cfg.kind == 0 : (v.cfg.kind == 1 && (1u << v.cfg.nt) == cbw))
+      out.push_back(v.cfg);
+  }
   return out;
 }
 
 ScanCfg scan_default(uint32_t B) {
-  return B == 1 ? ScanCfg{0, 4, 8, 0} : ScanCfg{1, 1, 4, 0};
+  if (B == 1) return ScanCfg{0, 2, 8, 1};
+  const uint32_t cbw = cbw_for(B);
+  const uint8_t lg = cbw == 8 ? 3 : cbw == 4 ? 2 : cbw == 2 ? 1 : 0;
+  return ScanCfg{1, 2, 8, lg};
 }
 
 hipError_t launch_scan(const ScanJob &job, const ScanCfg &cfg, hipStream_t s) {

@@ -184,7 +184,9 @@ def test_batch1_full_size(ctx):
 
 
 @pytest.mark.parametrize("log2n,K,R,C,B", [(10, 2, 200, 45, 1), (11, 1, 130, 300, 1),
-                                           (10, 2, 200, 45, 3), (10, 1, 97, 70, 17)])
+                                           (10, 2, 200, 45, 3), (10, 1, 97, 70, 5),
+                                           (10, 1, 97, 70, 17), (10, 2, 300, 41, 33),
+                                           (10, 1, 64, 33, 64)])
 def test_every_scan_variant_matches_oracle(ctx, log2n, K, R, C, B):
     from paper_2606_11536_amd import pir
     rg = ring(log2n, K)
