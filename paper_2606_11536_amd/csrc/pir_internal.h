@@ -102,7 +102,8 @@ struct ScanJob {
 // A scan kernel variant.  kind 0: batch-1 streaming kernel (jbw row blocks per
 // wave, unr k-blocks of loads in flight, nt = non-temporal loads); kind 1:
 // batched MFMA kernel (jbw row blocks per wave, unr = database-atom ring
-// depth, nt = log2 of the query column blocks per wave).
+// depth, nt = log2 of the query column blocks per wave in bits 0-3 and the
+// minimum waves per SIMD less one in bits 4-7).
 struct ScanCfg {
   uint8_t kind, jbw, unr, nt;
 };

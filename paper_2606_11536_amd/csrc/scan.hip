@@ -186,7 +186,7 @@ struct MfArgs {
   const uint8_t *qatoms;
   uint32_t *out;
   uint32_t B, n_cb;
-  uint32_t n_slots, n_jg, n_cbt;  // logical grid = n_cbt * n_slots * n_jg
+  uint32_t n_slots, n_jg, n_cbt;  // logical grid = n_slots * n_jg * n_cbt
   uint32_t total;
 };
 
@@ -195,8 +195,8 @@ struct MfArgs {
 // the atoms of contraction step ks + D are requested while step ks computes.
 // Steps past the end read a clamped (valid) atom and meet zero query atoms, so
 // the loop has no data-dependent branch and the load counters stay exact.
-template <int JBW, int CBW, int D>
-__global__ __launch_bounds__(256) void k_scan_mfma(const MfArgs a) {
+template <int JBW, int CBW, int D, int OCC>
+__global__ __launch_bounds__(256, OCC) void k_scan_mfma(const MfArgs a) {
   static_assert(D % kKCB == 0, "ring depth must be a multiple of the query chunk");
   constexpr uint32_t kBuf = kKCB * CBW * 64;  // uint4 per LDS buffer
   constexpr uint32_t kPer = (kBuf + 255) / 256;
@@ -204,9 +204,11 @@ __global__ __launch_bounds__(256) void k_scan_mfma(const MfArgs a) {
   const uint32_t L = xcd_logical(blockIdx.x, gridDim.x);
   if (L >= a.total) return;
   const DbDesc &db = a.db;
-  const uint32_t jg = L % a.n_jg;
-  const uint32_t rest = L / a.n_jg;
-  const uint32_t slot = rest % a.n_slots, cbt = rest / a.n_slots;
+  // column tiles of the same rows are adjacent, then row groups of one slot:
+  // a database atom's second read and a slot's query atoms come from L2
+  const uint32_t cbt = L % a.n_cbt;
+  const uint32_t rest = L / a.n_cbt;
+  const uint32_t jg = rest % a.n_jg, slot = rest / a.n_jg;
   const uint32_t k = slot >> db.log2n, t = slot & (db.N - 1);
   const DevPrime &P = db.primes[k];
   const uint32_t q = P.q;
@@ -341,7 +343,7 @@ hipError_t run_b1(const ScanJob &job, hipStream_t s) {
   return hipGetLastError();
 }
 
-template <int JBW, int CBW, int D>
+template <int JBW, int CBW, int D, int OCC>
 hipError_t run_mfma(const ScanJob &job, hipStream_t s) {
   const DbDesc &db = job.db;
   MfArgs a;
@@ -354,7 +356,7 @@ hipError_t run_mfma(const ScanJob &job, hipStream_t s) {
   a.n_jg = (db.n_jb + 4 * JBW - 1) / (4 * JBW);
   a.n_cbt = (a.n_cb + CBW - 1) / CBW;
   a.total = a.n_cbt * a.n_slots * a.n_jg;
-  k_scan_mfma<JBW, CBW, D><<<round8(a.total), 256, 0, s>>>(a);
+  k_scan_mfma<JBW, CBW, D, OCC><<<round8(a.total), 256, 0, s>>>(a);
   return hipGetLastError();
 }
 
@@ -365,8 +367,9 @@ struct Variant {
   ScanFn fn;
 };
 
-// ScanCfg for kind 1: jbw, unr = ring depth D, nt = log2(CBW).
-#define MF(J, C, D) {{1, J, D, C == 8 ? 3 : C == 4 ? 2 : C == 2 ? 1 : 0}, run_mfma<J, C, D>}
+// ScanCfg for kind 1: jbw, unr = ring depth D, nt = log2(CBW) | (OCC - 1) << 4.
+#define MF(J, C, D, O) \
+  {{1, J, D, (C == 8 ? 3 : C == 4 ? 2 : C == 2 ? 1 : 0) | ((O - 1) << 4)}, run_mfma<J, C, D, O>}
 const Variant kVariants[] = {
     // batch-1 streaming: (kind 0, jbw, unroll, nontemporal)
     {{0, 8, 4, 0}, run_b1<8, 4, false>}, {{0, 8, 8, 0}, run_b1<8, 8, false>},
@@ -374,10 +377,10 @@ const Variant kVariants[] = {
     {{0, 2, 8, 0}, run_b1<2, 8, false>}, {{0, 8, 4, 1}, run_b1<8, 4, true>},
     {{0, 4, 8, 1}, run_b1<4, 8, true>},  {{0, 2, 8, 1}, run_b1<2, 8, true>},
     // batched MFMA
-    MF(1, 1, 8), MF(2, 1, 8), MF(4, 1, 8),
-    MF(1, 2, 8), MF(2, 2, 8), MF(4, 2, 8),
-    MF(1, 4, 8), MF(2, 4, 8), MF(2, 4, 4),
-    MF(1, 8, 8), MF(2, 8, 8), MF(2, 8, 4), MF(1, 8, 4),
+    MF(1, 1, 8, 1), MF(2, 1, 8, 1), MF(4, 1, 8, 1), MF(4, 1, 8, 2),
+    MF(1, 2, 8, 1), MF(2, 2, 8, 1), MF(4, 2, 8, 1), MF(2, 2, 8, 2),
+    MF(1, 4, 8, 1), MF(2, 4, 8, 1), MF(2, 4, 8, 2), MF(2, 4, 4, 2), MF(4, 4, 8, 1),
+    MF(1, 8, 8, 1), MF(2, 8, 8, 1), MF(2, 8, 4, 1), MF(1, 8, 8, 2),
 };
 #undef MF
 
@@ -393,7 +396,8 @@ std::vector<ScanCfg> scan_candidates(uint32_t B) {
   std::vector<ScanCfg> out;
   const uint32_t cbw = cbw_for(B);
   for (const Variant &v : kVariants) {
-    if (B == 1 ? v.cfg.kind == 0 : (v.cfg.kind == 1 && (1u << v.cfg.nt) == cbw))
+    const uint32_t vc = 1u << (v.cfg.nt & 15);
+    if (B == 1 ? v.cfg.kind == 0 : (v.cfg.kind == 1 && (vc == cbw || 2 * vc == cbw)))
       out.push_back(v.cfg);
   }
   return out;
@@ -403,7 +407,7 @@ ScanCfg scan_default(uint32_t B) {
   if (B == 1) return ScanCfg{0, 2, 8, 1};
   const uint32_t cbw = cbw_for(B);
   const uint8_t lg = cbw == 8 ? 3 : cbw == 4 ? 2 : cbw == 2 ? 1 : 0;
-  return ScanCfg{1, 2, 8, lg};
+  return ScanCfg{1, 2, 8, (uint8_t)(lg == 3 ? 2 | 16 : lg)};
 }
 
 hipError_t launch_scan(const ScanJob &job, const ScanCfg &cfg, hipStream_t s) {
