@@ -197,6 +197,13 @@ pir_status pir_scan_select(pir_ctx *ctx, const pir_db *db, uint32_t B, uint32_t 
 pir_status pir_tune(pir_ctx *ctx, const pir_db *db, uint32_t B, pir_stream stream, char *report,
                     size_t report_len);
 
+/* Autotune the fused scan launches of pir_answer_batch for this job list:
+ * times every variant on the whole list (values do not affect timing) and
+ * keeps the fastest for later calls with jobs of the same shapes in the same
+ * order.  Waits for `stream`.  `report` as for pir_tune. */
+pir_status pir_tune_batch(pir_ctx *ctx, const pir_job *jobs, size_t n_jobs, pir_stream stream,
+                          char *report, size_t report_len);
+
 /* ---- measurement: per-stage kernel time with HIP events (off by default).
  * While enabled, pir_db_mul and pir_answer_batch bracket each stage's launch
  * with a pair of HIP events on the call's stream.  pir_profile_read waits for

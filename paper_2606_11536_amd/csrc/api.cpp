@@ -38,8 +38,9 @@ struct pir_ctx {
   std::vector<Rec> pending;
   double stage_ms[PIR_N_STAGES] = {};
   uint64_t stage_n[PIR_N_STAGES] = {};
-  // chosen scan variant per (N, K, R, C, B)
+  // chosen scan variant per (N, K, R, C, B), and per fused job list
   std::map<std::array<uint32_t, 5>, ScanCfg> scan_cfg;
+  std::map<std::vector<uint32_t>, ScanCfg> batch_cfg;
 };
 
 struct pir_db {
@@ -309,7 +310,80 @@ ScanCfg chosen_cfg(const pir_ctx *ctx, const DbDesc &d, uint32_t B) {
 }
 
 hipError_t run_scan(pir_ctx *ctx, const ScanJob &job, hipStream_t s) {
-  return launch_scan(job, chosen_cfg(ctx, job.db, job.B), s);
+  return launch_scan(&job, 1, chosen_cfg(ctx, job.db, job.B), s);
+}
+
+// Key of a fused group of scan jobs: the shapes of its jobs, in order.
+std::vector<uint32_t> group_key(const std::vector<ScanJob> &g) {
+  std::vector<uint32_t> key{(uint32_t)g.size()};
+  for (const ScanJob &j : g) {
+    const auto k = shape_key(j.db, j.B);
+    key.insert(key.end(), k.begin(), k.end());
+  }
+  return key;
+}
+
+// Variant for a fused group: the batch-tuned one, else (single job) the job's
+// own choice, else the default for the group's largest batch.
+ScanCfg group_cfg(const pir_ctx *ctx, const std::vector<ScanJob> &g) {
+  auto it = ctx->batch_cfg.find(group_key(g));
+  if (it != ctx->batch_cfg.end()) return it->second;
+  if (g.size() == 1) return chosen_cfg(ctx, g[0].db, g[0].B);
+  uint32_t bmax = 0;
+  for (const ScanJob &j : g) bmax = std::max(bmax, j.B);
+  return scan_default(bmax);
+}
+
+// Workspace layout and scan jobs of a job list (see pir_answer_batch).
+struct BatchPlan {
+  size_t shared_q = 0, own_q = 0, atoms = 0;
+  std::vector<ScanJob> b1, mf;      // fused groups: batch-1 kernel, batched kernel
+  std::vector<uint32_t *> qntt;     // per job: where its NTT-form query goes
+  std::vector<uint8_t *> qatoms;    // per job: its query atoms (batched kernel)
+  size_t bytes() const { return shared_q + own_q + atoms; }
+};
+
+size_t al256(size_t x) { return (x + 255) & ~(size_t)255; }
+
+pir_status plan_batch(pir_ctx *ctx, const pir_job *jobs, size_t n_jobs, BatchPlan &p) {
+  for (size_t n = 0; n < n_jobs; ++n) {
+    const pir_job &j = jobs[n];
+    if (!j.db || !j.query_coeff || !j.answer_coeff)
+      return fail(ctx, PIR_ERR_INVALID_ARG, "job %zu has a null pointer", n);
+    if (j.db->ctx != ctx)
+      return fail(ctx, PIR_ERR_INVALID_ARG, "job %zu: database belongs to another context", n);
+    if (j.B < 1 || j.B > PIR_MAX_BATCH)
+      return fail(ctx, PIR_ERR_INVALID_ARG, "job %zu: B=%u out of range", n, j.B);
+    const DbDesc &d = j.db->desc;
+    const size_t qb = al256((size_t)j.B * d.R * 2 * d.K * d.N * 4);
+    if (j.B == 1) p.own_q += qb;
+    else p.shared_q = std::max(p.shared_q, qb);
+    p.atoms += al256(query_atom_bytes(d, j.B));
+  }
+  return PIR_OK;
+}
+
+// Assign workspace regions (base = workspace) and build the scan groups.
+void place_batch(const pir_job *jobs, size_t n_jobs, uint8_t *base, BatchPlan &p) {
+  uint8_t *own = base + p.shared_q;
+  uint8_t *atoms = own + p.own_q;
+  p.qntt.assign(n_jobs, nullptr);
+  p.qatoms.assign(n_jobs, nullptr);
+  p.b1.clear();
+  p.mf.clear();
+  for (size_t n = 0; n < n_jobs; ++n) {
+    const pir_job &j = jobs[n];
+    const DbDesc &d = j.db->desc;
+    p.qntt[n] = (uint32_t *)base;
+    if (j.B == 1) {
+      p.qntt[n] = (uint32_t *)own;
+      own += al256((size_t)d.R * 2 * d.K * d.N * 4);
+    }
+    p.qatoms[n] = atoms;
+    atoms += al256(query_atom_bytes(d, j.B));
+    const ScanJob sj{d, p.qatoms[n], p.qntt[n], j.answer_coeff, j.B, 0, d.K * d.N};
+    (j.B == 1 ? p.b1 : p.mf).push_back(sj);
+  }
 }
 
 }  // namespace
@@ -553,7 +627,7 @@ pir_status pir_db_mul(pir_ctx *ctx, const pir_db *db, const uint32_t *query_ntt,
     StageTimer tm(ctx, s, PIR_STAGE_PACK);
     HIP_OR_FAIL(ctx, launch_pack_query(query_ntt, qatoms, B, db->R, db->desc.N, db->desc.K, s));
   }
-  ScanJob job{db->desc, qatoms, query_ntt, answer_ntt, B};
+  ScanJob job{db->desc, qatoms, query_ntt, answer_ntt, B, 0, db->desc.K * db->desc.N};
   {
     StageTimer tm(ctx, s, PIR_STAGE_SCAN);
     HIP_OR_FAIL(ctx, run_scan(ctx, job, s));
@@ -567,61 +641,89 @@ pir_status pir_answer_batch(pir_ctx *ctx, const pir_job *jobs, size_t n_jobs, pi
   // Workspace: one shared region for the NTT-form queries of batched jobs
   // (consumed by their pack before the next job's NTT), a region of its own
   // for each batch-1 job (read by its scan), and the query atoms of every job.
-  auto al = [](size_t x) { return (x + 255) & ~(size_t)255; };
-  size_t shared_q = 0, own_q = 0, sum_atoms = 0;
-  for (size_t n = 0; n < n_jobs; ++n) {
-    const pir_job &j = jobs[n];
-    if (!j.db || !j.query_coeff || !j.answer_coeff)
-      return fail(ctx, PIR_ERR_INVALID_ARG, "job %zu has a null pointer", n);
-    if (j.db->ctx != ctx)
-      return fail(ctx, PIR_ERR_INVALID_ARG, "job %zu: database belongs to another context", n);
-    if (j.B < 1 || j.B > PIR_MAX_BATCH)
-      return fail(ctx, PIR_ERR_INVALID_ARG, "job %zu: B=%u out of range", n, j.B);
-    const DbDesc &d = j.db->desc;
-    const size_t qb = al((size_t)j.B * d.R * 2 * d.K * d.N * 4);
-    if (j.B == 1) own_q += qb;
-    else shared_q = std::max(shared_q, qb);
-    sum_atoms += al(query_atom_bytes(d, j.B));
-  }
-  if (n_jobs == 0) return PIR_OK;
+  BatchPlan p;
+  pir_status st = plan_batch(ctx, jobs, n_jobs, p);
+  if (st != PIR_OK || n_jobs == 0) return st;
   DeviceGuard g(ctx->device);
-  pir_status st = ensure_ws(ctx, shared_q + own_q + sum_atoms);
-  if (st != PIR_OK) return st;
+  if ((st = ensure_ws(ctx, p.bytes())) != PIR_OK) return st;
   hipStream_t s = (hipStream_t)stream;
-  uint8_t *base = (uint8_t *)ctx->ws;
-  uint32_t *shared = (uint32_t *)base;
-  uint8_t *own = base + shared_q;
-  uint8_t *atoms = own + own_q;
-  std::vector<ScanJob> sj(n_jobs);
+  place_batch(jobs, n_jobs, (uint8_t *)ctx->ws, p);
   for (size_t n = 0; n < n_jobs; ++n) {
     const pir_job &j = jobs[n];
     const DbDesc &d = j.db->desc;
-    uint32_t *qntt = shared;
-    if (j.B == 1) {
-      qntt = (uint32_t *)own;
-      own += al((size_t)d.R * 2 * d.K * d.N * 4);
-    }
     {
       StageTimer tm(ctx, s, PIR_STAGE_NTT);
-      HIP_OR_FAIL(ctx, launch_ntt_copy(j.query_coeff, qntt, (size_t)j.B * d.R * 2 * d.K, d.K,
+      HIP_OR_FAIL(ctx, launch_ntt_copy(j.query_coeff, p.qntt[n], (size_t)j.B * d.R * 2 * d.K, d.K,
                                        d.log2n, d.primes, s));
     }
     if (j.B > 1) {
       StageTimer tm(ctx, s, PIR_STAGE_PACK);
-      HIP_OR_FAIL(ctx, launch_pack_query(qntt, atoms, j.B, d.R, d.N, d.K, s));
+      HIP_OR_FAIL(ctx, launch_pack_query(p.qntt[n], p.qatoms[n], j.B, d.R, d.N, d.K, s));
     }
-    sj[n] = ScanJob{d, atoms, qntt, j.answer_coeff, j.B};
-    atoms += al(query_atom_bytes(d, j.B));
   }
-  for (size_t n = 0; n < n_jobs; ++n) {
+  // the scans of all jobs: one fused launch per kernel kind
+  for (const std::vector<ScanJob> *grp : {&p.b1, &p.mf}) {
+    if (grp->empty()) continue;
     StageTimer tm(ctx, s, PIR_STAGE_SCAN);
-    HIP_OR_FAIL(ctx, run_scan(ctx, sj[n], s));
+    HIP_OR_FAIL(ctx, launch_scan(grp->data(), grp->size(), group_cfg(ctx, *grp), s));
   }
   for (size_t n = 0; n < n_jobs; ++n) {
-    const DbDesc &d = sj[n].db;
+    const DbDesc &d = jobs[n].db->desc;
     StageTimer tm(ctx, s, PIR_STAGE_INTT);
-    HIP_OR_FAIL(ctx, launch_ntt(sj[n].out, (size_t)sj[n].B * d.C * 2 * d.K, d.K, d.log2n, d.primes,
-                                true, s));
+    HIP_OR_FAIL(ctx, launch_ntt(jobs[n].answer_coeff, (size_t)jobs[n].B * d.C * 2 * d.K, d.K,
+                                d.log2n, d.primes, true, s));
+  }
+  return PIR_OK;
+}
+
+pir_status pir_tune_batch(pir_ctx *ctx, const pir_job *jobs, size_t n_jobs, pir_stream stream,
+                          char *report, size_t report_len) {
+  if (!ctx) return PIR_ERR_INVALID_ARG;
+  if (!jobs || n_jobs == 0) return fail(ctx, PIR_ERR_INVALID_ARG, "no jobs");
+  BatchPlan p;
+  pir_status st = plan_batch(ctx, jobs, n_jobs, p);
+  if (st != PIR_OK) return st;
+  DeviceGuard g(ctx->device);
+  if ((st = ensure_ws(ctx, p.bytes())) != PIR_OK) return st;
+  hipStream_t s = (hipStream_t)stream;
+  place_batch(jobs, n_jobs, (uint8_t *)ctx->ws, p);
+  HIP_OR_FAIL(ctx, hipMemsetAsync(ctx->ws, 0, p.bytes(), s));
+  hipEvent_t e0, e1;
+  HIP_OR_FAIL(ctx, hipEventCreate(&e0));
+  HIP_OR_FAIL(ctx, hipEventCreate(&e1));
+  std::string rep;
+  for (const std::vector<ScanJob> *grp : {&p.b1, &p.mf}) {
+    if (grp->empty()) continue;
+    uint32_t bmax = 0;
+    for (const ScanJob &j : *grp) bmax = std::max(bmax, j.B);
+    const std::vector<ScanCfg> cands = scan_candidates(bmax);
+    float best = 1e30f;
+    size_t best_i = 0;
+    for (size_t i = 0; i < cands.size(); ++i) {
+      HIP_OR_FAIL(ctx, launch_scan(grp->data(), grp->size(), cands[i], s));
+      HIP_OR_FAIL(ctx, hipEventRecord(e0, s));
+      for (int r = 0; r < 3; ++r) HIP_OR_FAIL(ctx, launch_scan(grp->data(), grp->size(), cands[i], s));
+      HIP_OR_FAIL(ctx, hipEventRecord(e1, s));
+      HIP_OR_FAIL(ctx, hipEventSynchronize(e1));
+      float ms = 0.f;
+      HIP_OR_FAIL(ctx, hipEventElapsedTime(&ms, e0, e1));
+      ms /= 3;
+      char buf[96];
+      snprintf(buf, sizeof buf, "%s%zu:%u/%u/%u/%u=%.4f;", grp == &p.b1 ? "b1 " : "mf ", i,
+               cands[i].kind, cands[i].jbw, cands[i].unr, cands[i].nt, ms);
+      rep += buf;
+      if (ms < best) best = ms, best_i = i;
+    }
+    ctx->batch_cfg[group_key(*grp)] = cands[best_i];
+    char buf[32];
+    snprintf(buf, sizeof buf, "best=%zu;", best_i);
+    rep += buf;
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  if (report && report_len) {
+    std::strncpy(report, rep.c_str(), report_len - 1);
+    report[report_len - 1] = 0;
   }
   return PIR_OK;
 }
@@ -656,7 +758,7 @@ pir_status pir_tune(pir_ctx *ctx, const pir_db *db, uint32_t B, pir_stream strea
   uint8_t *base = (uint8_t *)ctx->ws;
   // Timing does not depend on values; start from a defined state all the same.
   HIP_OR_FAIL(ctx, hipMemsetAsync(base, 0, qb + ab + ob, s));
-  ScanJob job{d, base + qb, (const uint32_t *)base, (uint32_t *)(base + qb + ab), B};
+  ScanJob job{d, base + qb, (const uint32_t *)base, (uint32_t *)(base + qb + ab), B, 0, d.K * d.N};
   const std::vector<ScanCfg> cands = scan_candidates(B);
   hipEvent_t e0, e1;
   HIP_OR_FAIL(ctx, hipEventCreate(&e0));
@@ -666,9 +768,9 @@ pir_status pir_tune(pir_ctx *ctx, const pir_db *db, uint32_t B, pir_stream strea
   size_t best_i = 0;
   const int reps = 3;
   for (size_t i = 0; i < cands.size(); ++i) {
-    HIP_OR_FAIL(ctx, launch_scan(job, cands[i], s));  // warm-up
+    HIP_OR_FAIL(ctx, launch_scan(&job, 1, cands[i], s));  // warm-up
     HIP_OR_FAIL(ctx, hipEventRecord(e0, s));
-    for (int r = 0; r < reps; ++r) HIP_OR_FAIL(ctx, launch_scan(job, cands[i], s));
+    for (int r = 0; r < reps; ++r) HIP_OR_FAIL(ctx, launch_scan(&job, 1, cands[i], s));
     HIP_OR_FAIL(ctx, hipEventRecord(e1, s));
     HIP_OR_FAIL(ctx, hipEventSynchronize(e1));
     float ms = 0.f;

@@ -90,13 +90,15 @@ hipError_t launch_read_db(const DbDesc &db, uint32_t i0, uint32_t ni, uint32_t j
 hipError_t launch_pack_query(const uint32_t *q_ntt, uint8_t *qatoms, uint32_t B, uint32_t R,
                              uint32_t N, uint32_t K, hipStream_t s);
 
-// One scan job for the scan kernels.
+// One scan job for the scan kernels: the slots [slot0, slot0 + n_slots) of
+// the flat slot index k * N + t (all K*N slots for a whole scan).
 struct ScanJob {
   DbDesc db;
-  const uint8_t *qatoms;   // query atoms of this job (B > 1)
-  const uint32_t *q_ntt;   // NTT-form query [1][R][2][K][N] (B == 1)
+  const uint8_t *qatoms;   // query atoms of this job (batched kernel)
+  const uint32_t *q_ntt;   // NTT-form query [1][R][2][K][N] (batch-1 kernel)
   uint32_t *out;           // answer NTT form [B][C][2][K][N]
   uint32_t B;
+  uint32_t slot0, n_slots;
 };
 
 // A scan kernel variant.  kind 0: batch-1 streaming kernel (jbw row blocks per
@@ -110,6 +112,8 @@ struct ScanCfg {
 
 std::vector<ScanCfg> scan_candidates(uint32_t B);
 ScanCfg scan_default(uint32_t B);
-hipError_t launch_scan(const ScanJob &job, const ScanCfg &cfg, hipStream_t s);
+// Scan every job with one variant; jobs are fused into launches of up to 8.
+// kind 0 needs B == 1 for every job, kind 1 any B (query atoms).
+hipError_t launch_scan(const ScanJob *jobs, size_t n, const ScanCfg &cfg, hipStream_t s);
 
 }  // namespace pir

@@ -27,6 +27,8 @@
 //    owns JBW x 8 database rows and CBW x 8 query columns; database atoms come
 //    through a register ring D contraction steps deep, query atoms through
 //    double-buffered LDS chunks shared by the block's four waves.
+#include <algorithm>
+
 #include "device_util.h"
 #include "pir_internal.h"
 
@@ -38,14 +40,34 @@ typedef int v16i __attribute__((ext_vector_type(16)));
 
 constexpr uint32_t kB1Chunk = 64;  // query ibs split into LDS per chunk (16 KiB)
 
-struct B1Args {
+// Scan launches take a table of up to kMaxFused jobs; the logical block
+// index space is the concatenation of the jobs' spaces (job j owns logical
+// blocks [first, first + blocks)).  A block finds its job by a uniform
+// search of the table in the kernel-argument segment.
+constexpr int kMaxFused = 8;
+
+struct B1Job {
   DbDesc db;
   const uint32_t *q;  // NTT-form query [1][R][2][K][N]
   uint32_t *out;      // answer [1][C][2][K][N]
-  uint32_t n_slots;   // K * N
+  uint32_t slot0, n_slots;  // slots scanned: [slot0, slot0 + n_slots)
   uint32_t jpb;       // jbs per block
-  uint32_t total;     // logical blocks
+  uint32_t first;     // first logical block of this job
 };
+
+struct B1Args {
+  B1Job jobs[kMaxFused];
+  uint32_t n_jobs, total;
+};
+
+template <typename Args>
+__device__ __forceinline__ uint32_t find_job(const Args &a, uint32_t L) {
+  uint32_t jid = 0;
+#pragma unroll
+  for (int j = 1; j < kMaxFused; ++j)
+    if ((uint32_t)j < a.n_jobs && L >= a.jobs[j].first) jid = j;
+  return jid;
+}
 
 // Reduce the lane's partial sum s over the 4 lanes b = 0..3 (lane bits 0,1).
 // Input s in [0, 2q); output in [0, q).
@@ -68,12 +90,14 @@ __device__ __forceinline__ v4i load_atom16(const uint8_t *p) {
 }
 
 template <int JBW, int UNR, bool NT>
-__global__ __launch_bounds__(256) void k_scan_b1(const B1Args a) {
+__global__ __launch_bounds__(256) void k_scan_b1(const B1Args args) {
   __shared__ uint32_t sq[kB1Chunk * 64];
-  const uint32_t L = xcd_logical(blockIdx.x, gridDim.x);
-  if (L >= a.total) return;
+  const uint32_t Lg = xcd_logical(blockIdx.x, gridDim.x);
+  if (Lg >= args.total) return;
+  const B1Job &a = args.jobs[find_job(args, Lg)];
+  const uint32_t L = Lg - a.first;
   const DbDesc &db = a.db;
-  const uint32_t slot = L % a.n_slots, jchunk = L / a.n_slots;
+  const uint32_t slot = a.slot0 + L % a.n_slots, jchunk = L / a.n_slots;
   const uint32_t k = slot >> db.log2n, t = slot & (db.N - 1);
   const DevPrime &P = db.primes[k];
   const uint32_t q = P.q;
@@ -181,13 +205,18 @@ __global__ __launch_bounds__(256) void k_scan_b1(const B1Args a) {
 // ---------------------------------------------------------------------------
 constexpr uint32_t kKCB = 4;  // contraction atoms per staged query chunk
 
-struct MfArgs {
+struct MfJob {
   DbDesc db;
-  const uint8_t *qatoms;
-  uint32_t *out;
+  const uint8_t *qatoms;  // query atoms [K][N][n_ib][n_cb]
+  uint32_t *out;          // answer [B][C][2][K][N]
   uint32_t B, n_cb;
-  uint32_t n_slots, n_jg, n_cbt;  // logical grid = n_slots * n_jg * n_cbt
-  uint32_t total;
+  uint32_t slot0, n_slots, n_jg, n_cbt;  // job's logical blocks = n_slots * n_jg * n_cbt
+  uint32_t first;
+};
+
+struct MfArgs {
+  MfJob jobs[kMaxFused];
+  uint32_t n_jobs, total;
 };
 
 // JBW database row blocks x CBW query column blocks per wave; the four waves of
@@ -196,19 +225,21 @@ struct MfArgs {
 // Steps past the end read a clamped (valid) atom and meet zero query atoms, so
 // the loop has no data-dependent branch and the load counters stay exact.
 template <int JBW, int CBW, int D, int OCC>
-__global__ __launch_bounds__(256, OCC) void k_scan_mfma(const MfArgs a) {
+__global__ __launch_bounds__(256, OCC) void k_scan_mfma(const MfArgs args) {
   static_assert(D % kKCB == 0, "ring depth must be a multiple of the query chunk");
   constexpr uint32_t kBuf = kKCB * CBW * 64;  // uint4 per LDS buffer
   constexpr uint32_t kPer = (kBuf + 255) / 256;
   __shared__ uint4 sq[2 * kBuf];
-  const uint32_t L = xcd_logical(blockIdx.x, gridDim.x);
-  if (L >= a.total) return;
+  const uint32_t Lg = xcd_logical(blockIdx.x, gridDim.x);
+  if (Lg >= args.total) return;
+  const MfJob &a = args.jobs[find_job(args, Lg)];
+  const uint32_t L = Lg - a.first;
   const DbDesc &db = a.db;
   // column tiles of the same rows are adjacent, then row groups of one slot:
   // a database atom's second read and a slot's query atoms come from L2
   const uint32_t cbt = L % a.n_cbt;
   const uint32_t rest = L / a.n_cbt;
-  const uint32_t jg = rest % a.n_jg, slot = rest / a.n_jg;
+  const uint32_t jg = rest % a.n_jg, slot = a.slot0 + rest / a.n_jg;
   const uint32_t k = slot >> db.log2n, t = slot & (db.N - 1);
   const DevPrime &P = db.primes[k];
   const uint32_t q = P.q;
@@ -329,38 +360,55 @@ __global__ __launch_bounds__(256, OCC) void k_scan_mfma(const MfArgs a) {
 inline uint32_t round8(uint32_t x) { return (x + 7) / 8 * 8; }
 
 template <int JBW, int UNR, bool NT>
-hipError_t run_b1(const ScanJob &job, hipStream_t s) {
-  const DbDesc &db = job.db;
-  B1Args a;
-  a.db = db;
-  a.q = job.q_ntt;
-  a.out = job.out;
-  a.n_slots = db.K * db.N;
-  a.jpb = 4 * JBW;
-  const uint32_t n_jchunks = (db.n_jb + a.jpb - 1) / a.jpb;
-  a.total = a.n_slots * n_jchunks;
-  k_scan_b1<JBW, UNR, NT><<<round8(a.total), 256, 0, s>>>(a);
+hipError_t run_b1(const ScanJob *jobs, size_t n, hipStream_t s) {
+  B1Args a{};
+  uint32_t total = 0;
+  for (size_t i = 0; i < n; ++i) {
+    const ScanJob &job = jobs[i];
+    B1Job &b = a.jobs[i];
+    b.db = job.db;
+    b.q = job.q_ntt;
+    b.out = job.out;
+    b.slot0 = job.slot0;
+    b.n_slots = job.n_slots;
+    b.jpb = 4 * JBW;
+    b.first = total;
+    total += b.n_slots * ((job.db.n_jb + b.jpb - 1) / b.jpb);
+  }
+  a.n_jobs = (uint32_t)n;
+  a.total = total;
+  if (total == 0) return hipSuccess;
+  k_scan_b1<JBW, UNR, NT><<<round8(total), 256, 0, s>>>(a);
   return hipGetLastError();
 }
 
 template <int JBW, int CBW, int D, int OCC>
-hipError_t run_mfma(const ScanJob &job, hipStream_t s) {
-  const DbDesc &db = job.db;
-  MfArgs a;
-  a.db = db;
-  a.qatoms = job.qatoms;
-  a.out = job.out;
-  a.B = job.B;
-  a.n_cb = (2 * job.B + kCB - 1) / kCB;
-  a.n_slots = db.K * db.N;
-  a.n_jg = (db.n_jb + 4 * JBW - 1) / (4 * JBW);
-  a.n_cbt = (a.n_cb + CBW - 1) / CBW;
-  a.total = a.n_cbt * a.n_slots * a.n_jg;
-  k_scan_mfma<JBW, CBW, D, OCC><<<round8(a.total), 256, 0, s>>>(a);
+hipError_t run_mfma(const ScanJob *jobs, size_t n, hipStream_t s) {
+  MfArgs a{};
+  uint32_t total = 0;
+  for (size_t i = 0; i < n; ++i) {
+    const ScanJob &job = jobs[i];
+    MfJob &m = a.jobs[i];
+    m.db = job.db;
+    m.qatoms = job.qatoms;
+    m.out = job.out;
+    m.B = job.B;
+    m.n_cb = (2 * job.B + kCB - 1) / kCB;
+    m.slot0 = job.slot0;
+    m.n_slots = job.n_slots;
+    m.n_jg = (job.db.n_jb + 4 * JBW - 1) / (4 * JBW);
+    m.n_cbt = (m.n_cb + CBW - 1) / CBW;
+    m.first = total;
+    total += m.n_cbt * m.n_slots * m.n_jg;
+  }
+  a.n_jobs = (uint32_t)n;
+  a.total = total;
+  if (total == 0) return hipSuccess;
+  k_scan_mfma<JBW, CBW, D, OCC><<<round8(total), 256, 0, s>>>(a);
   return hipGetLastError();
 }
 
-typedef hipError_t (*ScanFn)(const ScanJob &, hipStream_t);
+typedef hipError_t (*ScanFn)(const ScanJob *, size_t, hipStream_t);
 
 struct Variant {
   ScanCfg cfg;
@@ -410,11 +458,21 @@ ScanCfg scan_default(uint32_t B) {
   return ScanCfg{1, 2, 8, (uint8_t)(lg == 3 ? 2 | 16 : lg)};
 }
 
-hipError_t launch_scan(const ScanJob &job, const ScanCfg &cfg, hipStream_t s) {
-  if ((cfg.kind == 0) != (job.B == 1)) return hipErrorInvalidValue;
-  for (const Variant &v : kVariants)
-    if (v.cfg.kind == cfg.kind && v.cfg.jbw == cfg.jbw && v.cfg.unr == cfg.unr && v.cfg.nt == cfg.nt)
-      return v.fn(job, s);
+hipError_t launch_scan(const ScanJob *jobs, size_t n, const ScanCfg &cfg, hipStream_t s) {
+  for (size_t i = 0; i < n; ++i) {
+    const ScanJob &j = jobs[i];
+    if ((cfg.kind == 0) != (j.B == 1)) return hipErrorInvalidValue;
+    if (j.n_slots == 0 || j.slot0 + j.n_slots > j.db.K * j.db.N) return hipErrorInvalidValue;
+  }
+  for (const Variant &v : kVariants) {
+    if (v.cfg.kind != cfg.kind || v.cfg.jbw != cfg.jbw || v.cfg.unr != cfg.unr || v.cfg.nt != cfg.nt)
+      continue;
+    for (size_t i = 0; i < n; i += kMaxFused) {
+      const hipError_t e = v.fn(jobs + i, std::min<size_t>(kMaxFused, n - i), s);
+      if (e != hipSuccess) return e;
+    }
+    return hipSuccess;
+  }
   return hipErrorInvalidValue;
 }
 

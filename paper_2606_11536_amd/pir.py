@@ -64,6 +64,8 @@ SIGNATURES = {
     "pir_scan_variants": (ct.c_uint32, [_U32]),
     "pir_scan_select": (ct.c_int, [_P, _P, _U32, _U32]),
     "pir_tune": (ct.c_int, [_P, _P, _U32, _P, ct.c_char_p, ct.c_size_t]),
+    "pir_tune_batch": (ct.c_int, [_P, ct.POINTER(CJob), ct.c_size_t, _P, ct.c_char_p,
+                                  ct.c_size_t]),
     "pir_profile_enable": (ct.c_int, [_P, ct.c_int]),
     "pir_profile_read": (ct.c_int, [_P, _U32, ct.POINTER(ct.c_double),
                                     ct.POINTER(ct.c_uint64)]),
@@ -257,12 +259,24 @@ class Context:
         _check(lib.pir_db_mul(self.handle, db.handle, _ptr(query_ntt), B, _ptr(answer_ntt),
                               _stream(stream)), self.handle)
 
-    def answer_batch(self, jobs, stream=None) -> None:
-        """Fused batch: jobs = [(db, B, query_coeff, answer_coeff), ...] (coefficient form)."""
+    @staticmethod
+    def _jobs(jobs):
         arr = (CJob * len(jobs))()
         for n, (db, B, qc, ac) in enumerate(jobs):
             arr[n] = CJob(db.handle, B, qc.data_ptr(), ac.data_ptr())
-        _check(lib.pir_answer_batch(self.handle, arr, len(jobs), _stream(stream)), self.handle)
+        return arr
+
+    def answer_batch(self, jobs, stream=None) -> None:
+        """Fused batch: jobs = [(db, B, query_coeff, answer_coeff), ...] (coefficient form)."""
+        _check(lib.pir_answer_batch(self.handle, self._jobs(jobs), len(jobs), _stream(stream)),
+               self.handle)
+
+    def tune_batch(self, jobs, stream=None) -> str:
+        """Autotune the fused scan launches for this job list; returns the report."""
+        buf = ct.create_string_buffer(8192)
+        _check(lib.pir_tune_batch(self.handle, self._jobs(jobs), len(jobs), _stream(stream), buf,
+                                  len(buf)), self.handle)
+        return buf.value.decode()
 
     def profile(self, enable: bool = True) -> None:
         """Turn per-stage HIP-event timing on (resets the sums) or off."""

@@ -208,3 +208,39 @@ def test_every_scan_variant_matches_oracle(ctx, log2n, K, R, C, B):
     out = empty_dev((B, C, 2, K, rg.N))
     ctx.db_mul(db, qd, B, out)
     assert np.array_equal(to_host(out), exp)
+
+
+def test_fused_batch_many_jobs_and_tuning(ctx):
+    """Eleven jobs over four databases (mixed N, R, C, B, including B = 1): the
+    fused scan launches split at eight jobs; every variant choice made by
+    pir_tune_batch gives the same bytes."""
+    specs = [(10, 2, 90, 19), (11, 2, 64, 33), (12, 2, 20, 12), (10, 1, 130, 9)]
+    Bs = [1, 3, 2, 7, 1, 12, 5, 4, 1, 9, 2]
+    rng = np.random.default_rng(21)
+    dbs = []
+    for n, (log2n, K, R, C) in enumerate(specs):
+        rg = ring(log2n, K)
+        raw = synth.db_bytes(900 + n, R, C, rg.N)
+        dbs.append((rg, raw, ctx.load_db(rg.pir_params(), raw, R, C), R, C))
+    jobs, checks = [], []
+    for n, B in enumerate(Bs):
+        rg, raw, db, R, C = dbs[n % len(dbs)]
+        qc = residues(rng, (B, R, 2), rg)
+        out = empty_dev((B, C, 2, rg.K, rg.N))
+        jobs.append((db, B, to_dev(qc), out))
+        checks.append((rg, raw, qc))
+    exp = []
+    for rg, raw, qc in checks:
+        y = osc.db_mul(osc.db_ntt(raw, rg.primes, rg.psis), osc.query_ntt(qc, rg.primes, rg.psis),
+                       rg.primes)
+        exp.append(osc.answer_intt(y, rg.primes, rg.psis))
+    ctx.answer_batch(jobs)
+    for (_, _, _, out), e in zip(jobs, exp):
+        assert np.array_equal(to_host(out), e)
+    report = ctx.tune_batch(jobs)
+    assert "best=" in report
+    for (_, _, _, out) in jobs:
+        out.zero_()
+    ctx.answer_batch(jobs)
+    for (_, _, _, out), e in zip(jobs, exp):
+        assert np.array_equal(to_host(out), e)
