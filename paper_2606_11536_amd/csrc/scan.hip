@@ -297,28 +297,41 @@ __global__ __launch_bounds__(256, OCC) void k_scan_mfma(const MfArgs args) {
   stage_store(sq, st);
   __syncthreads();
 
+  // Query operands of the current step; those of the next step are read from
+  // LDS while the current step's MFMAs run (within a chunk; across a chunk
+  // boundary they are read right after the barrier that publishes the chunk).
+  v4i bcur[CBW], bnext[CBW];
+  auto b_read = [&](const uint4 *src, v4i (&bv)[CBW]) {
+#pragma unroll
+    for (int c = 0; c < CBW; ++c) {
+      const uint4 u = src[c * 64 + lane];
+      bv[c] = v4i{(int)u.x, (int)u.y, (int)u.z, (int)u.w};
+    }
+  };
+  b_read(sq, bcur);
   const uint32_t n_steps = (n_ib + D - 1) / D * D;
   for (uint32_t ks0 = 0; ks0 < n_steps; ks0 += D) {
 #pragma unroll
     for (int d = 0; d < D; ++d) {
       const uint32_t ks = ks0 + d;
       const uint32_t chunk = ks / kKCB;
-      if (d % kKCB == 0) stage_load(ks + kKCB, st);  // next chunk, in flight during this one
-      const uint4 *buf = sq + (chunk & 1) * kBuf + (d % kKCB) * CBW * 64;
+      const int kk = d % kKCB;
+      if (kk == 0) stage_load(ks + kKCB, st);  // next chunk, in flight during this one
+      if (kk + 1 < (int)kKCB) b_read(sq + (chunk & 1) * kBuf + (kk + 1) * CBW * 64, bnext);
 #pragma unroll
-      for (int c = 0; c < CBW; ++c) {
-        const uint4 u = buf[c * 64 + lane];
-        const v4i bv = v4i{(int)u.x, (int)u.y, (int)u.z, (int)u.w};
+      for (int c = 0; c < CBW; ++c)
 #pragma unroll
         for (int w = 0; w < JBW; ++w)
-          acc[w][c] = __builtin_amdgcn_mfma_i32_32x32x32_i8(ring[d][w], bv, acc[w][c], 0, 0, 0);
-      }
+          acc[w][c] = __builtin_amdgcn_mfma_i32_32x32x32_i8(ring[d][w], bcur[c], acc[w][c], 0, 0, 0);
 #pragma unroll
       for (int w = 0; w < JBW; ++w) ring[d][w] = a_load(w, ks + D);
-      if (d % kKCB == kKCB - 1) {
+      if (kk == (int)kKCB - 1) {
         stage_store(sq + ((chunk + 1) & 1) * kBuf, st);
         __syncthreads();
+        b_read(sq + ((chunk + 1) & 1) * kBuf, bnext);
       }
+#pragma unroll
+      for (int c = 0; c < CBW; ++c) bcur[c] = bnext[c];
     }
   }
 
@@ -427,8 +440,8 @@ const Variant kVariants[] = {
     // batched MFMA
     MF(1, 1, 8, 1), MF(2, 1, 8, 1), MF(4, 1, 8, 1), MF(4, 1, 8, 2),
     MF(1, 2, 8, 1), MF(2, 2, 8, 1), MF(4, 2, 8, 1), MF(2, 2, 8, 2),
-    MF(1, 4, 8, 1), MF(2, 4, 8, 1), MF(2, 4, 8, 2), MF(2, 4, 4, 2), MF(4, 4, 8, 1),
-    MF(1, 8, 8, 1), MF(2, 8, 8, 1), MF(2, 8, 4, 1), MF(1, 8, 8, 2),
+    MF(1, 4, 8, 1), MF(2, 4, 8, 1), MF(2, 4, 4, 2), MF(4, 4, 8, 1), MF(4, 4, 4, 1),
+    MF(1, 8, 8, 1), MF(2, 8, 8, 1), MF(2, 8, 4, 1), MF(1, 8, 4, 2),
 };
 #undef MF
 
@@ -455,7 +468,7 @@ ScanCfg scan_default(uint32_t B) {
   if (B == 1) return ScanCfg{0, 2, 8, 1};
   const uint32_t cbw = cbw_for(B);
   const uint8_t lg = cbw == 8 ? 3 : cbw == 4 ? 2 : cbw == 2 ? 1 : 0;
-  return ScanCfg{1, 2, 8, (uint8_t)(lg == 3 ? 2 | 16 : lg)};
+  return ScanCfg{1, 2, 8, lg};
 }
 
 hipError_t launch_scan(const ScanJob *jobs, size_t n, const ScanCfg &cfg, hipStream_t s) {
