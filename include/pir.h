@@ -204,6 +204,42 @@ pir_status pir_tune(pir_ctx *ctx, const pir_db *db, uint32_t B, pir_stream strea
 pir_status pir_tune_batch(pir_ctx *ctx, const pir_job *jobs, size_t n_jobs, pir_stream stream,
                           char *report, size_t report_len);
 
+/* ---- a6: continuous-batching server (Sec. 2.5 multi-client batching;
+ * Sec. 4.4 stream-wise buffering).  The database's K*N (prime, slot) pairs are
+ * cut into n_chunks ranges scanned round-robin, one range per step.  A query
+ * is admitted at a step boundary into a free column slot (forward NTT and
+ * limb packing into its own columns), takes part in every step's scan launch
+ * with all other active queries, and finishes after n_chunks steps: inverse
+ * NTT, copy to its answer buffer, completion event.  A query's answer is the
+ * same bytes alone or among others.  State per column slot: query limbs
+ * (R_pad*2*K*N bytes) and an answer (C*2*K*N*4 bytes); max_batch is lowered
+ * to what the context's HBM budget admits (BUDGET if not even one fits). */
+typedef struct pir_server pir_server;
+
+pir_status pir_server_create(pir_ctx *ctx, const pir_db *db, uint32_t max_batch, uint32_t n_chunks,
+                             pir_server **out);
+void pir_server_destroy(pir_server *srv);
+
+/* Queue a query (device [R][2][K][N], coefficient form) whose answer goes to
+ * answer_coeff (device [C][2][K][N]).  Launches nothing.  Both buffers must
+ * stay valid until the ticket reports done. */
+pir_status pir_server_submit(pir_server *srv, const uint32_t *query_coeff, uint32_t *answer_coeff,
+                             uint64_t *ticket);
+
+/* One step on `stream`: admit queued queries into free slots, scan the next
+ * range for all active queries, finish queries that completed their lap.
+ * Asynchronous.  *admitted / *finished (may be NULL) count this step's events. */
+pir_status pir_server_step(pir_server *srv, pir_stream stream, uint32_t *admitted,
+                           uint32_t *finished);
+
+/* *done = 1 once the ticket's answer is in its buffer (reported once; the
+ * ticket is then forgotten), else 0.  INVALID_ARG for unknown tickets. */
+pir_status pir_server_poll(pir_server *srv, uint64_t ticket, int *done);
+
+/* Admission limit after the budget, queries active and queued, next range. */
+pir_status pir_server_info(const pir_server *srv, uint32_t *max_batch, uint32_t *active,
+                           uint32_t *queued, uint32_t *next_chunk);
+
 /* ---- measurement: per-stage kernel time with HIP events (off by default).
  * While enabled, pir_db_mul and pir_answer_batch bracket each stage's launch
  * with a pair of HIP events on the call's stream.  pir_profile_read waits for

@@ -15,49 +15,16 @@
 #include <string>
 #include <vector>
 
+#include "ctx.h"
 #include "pir_internal.h"
 
 using namespace pir;
 
-struct pir_ctx {
-  int device = 0;
-  int num_cus = 0;
-  size_t budget = 0;  // 0 = unlimited
-  size_t held = 0;    // device bytes held (databases + workspace + tables)
-  std::string err;
-  void *ws = nullptr;
-  size_t ws_bytes = 0;
-  std::map<std::pair<uint32_t, uint32_t>, uint32_t *> tw_tables;  // (log2n, q) -> [4][N]
-  std::map<std::vector<uint32_t>, DevPrime *> prime_sets;         // (log2n, q...) -> [K]
-  // stage profiling
-  bool prof = false;
-  struct Rec {
-    uint32_t stage;
-    hipEvent_t a, b;
-  };
-  std::vector<Rec> pending;
-  double stage_ms[PIR_N_STAGES] = {};
-  uint64_t stage_n[PIR_N_STAGES] = {};
-  // chosen scan variant per (N, K, R, C, B), and per fused job list
-  std::map<std::array<uint32_t, 5>, ScanCfg> scan_cfg;
-  std::map<std::vector<uint32_t>, ScanCfg> batch_cfg;
-};
-
-struct pir_db {
-  pir_ctx *ctx = nullptr;
-  pir_params params{};
-  uint32_t R = 0, C = 0;
-  size_t bytes = 0;
-  uint8_t *atoms = nullptr;
-  DbDesc desc{};
-};
-
-namespace {
+namespace pir {
 
 // Message of the last failure that had no context to hold it (per thread).
 thread_local std::string g_noctx_err;
 
-// ---------------------------------------------------------------- errors --
 pir_status fail(pir_ctx *ctx, pir_status s, const char *fmt, ...) {
   char buf[512];
   va_list ap;
@@ -68,24 +35,9 @@ pir_status fail(pir_ctx *ctx, pir_status s, const char *fmt, ...) {
   return s;
 }
 
-#define HIP_OR_FAIL(ctx, expr)                                                           \
-  do {                                                                                   \
-    hipError_t e_ = (expr);                                                              \
-    if (e_ != hipSuccess)                                                                \
-      return fail((ctx), PIR_ERR_DEVICE, "%s failed: %s", #expr, hipGetErrorString(e_)); \
-  } while (0)
+}  // namespace pir
 
-struct DeviceGuard {
-  int prev = -1;
-  explicit DeviceGuard(int dev) {
-    if (hipGetDevice(&prev) != hipSuccess) prev = -1;
-    if (prev != dev) (void)hipSetDevice(dev);
-  }
-  ~DeviceGuard() {
-    int cur = -1;
-    if (prev >= 0 && hipGetDevice(&cur) == hipSuccess && cur != prev) (void)hipSetDevice(prev);
-  }
-};
+namespace {
 
 // ------------------------------------------------------- number theory ----
 uint64_t mulmod(uint64_t a, uint64_t b, uint64_t m) {
@@ -177,6 +129,9 @@ pir_status check_params(pir_ctx *ctx, const pir_params *p) {
   return PIR_OK;
 }
 
+}  // namespace
+
+namespace pir {
 // ------------------------------------------------------- device memory ----
 pir_status dev_alloc(pir_ctx *ctx, void **p, size_t bytes, const char *what) {
   if (ctx->budget && ctx->held + bytes > ctx->budget)
@@ -196,6 +151,10 @@ void dev_free(pir_ctx *ctx, void *p, size_t bytes) {
   ctx->held -= bytes;
 }
 
+}  // namespace pir
+
+namespace {
+
 pir_status ensure_ws(pir_ctx *ctx, size_t bytes) {
   if (ctx->ws_bytes >= bytes) return PIR_OK;
   HIP_OR_FAIL(ctx, hipDeviceSynchronize());
@@ -209,6 +168,9 @@ pir_status ensure_ws(pir_ctx *ctx, size_t bytes) {
   return PIR_OK;
 }
 
+}  // namespace
+
+namespace pir {
 // Device table of per-prime constants for (log2n, primes).
 pir_status prime_set(pir_ctx *ctx, const pir_params *p, const DevPrime **out) {
   std::vector<uint32_t> key{p->log2_n};
@@ -265,6 +227,10 @@ pir_status prime_set(pir_ctx *ctx, const pir_params *p, const DevPrime **out) {
   return PIR_OK;
 }
 
+}  // namespace pir
+
+namespace {
+
 // Brackets one stage launch with HIP events when profiling is on.
 struct StageTimer {
   pir_ctx *ctx;
@@ -304,10 +270,14 @@ size_t query_atom_bytes(const DbDesc &d, uint32_t B) {
 
 std::array<uint32_t, 5> shape_key(const DbDesc &d, uint32_t B) { return {d.N, d.K, d.R, d.C, B}; }
 
-ScanCfg chosen_cfg(const pir_ctx *ctx, const DbDesc &d, uint32_t B) {
+}  // namespace
+
+ScanCfg pir::chosen_cfg(const pir_ctx *ctx, const DbDesc &d, uint32_t B) {
   auto it = ctx->scan_cfg.find(shape_key(d, B));
   return it != ctx->scan_cfg.end() ? it->second : scan_default(B);
 }
+
+namespace {
 
 hipError_t run_scan(pir_ctx *ctx, const ScanJob &job, hipStream_t s) {
   return launch_scan(&job, 1, chosen_cfg(ctx, job.db, job.B), s);
@@ -381,7 +351,7 @@ void place_batch(const pir_job *jobs, size_t n_jobs, uint8_t *base, BatchPlan &p
     }
     p.qatoms[n] = atoms;
     atoms += al256(query_atom_bytes(d, j.B));
-    const ScanJob sj{d, p.qatoms[n], p.qntt[n], j.answer_coeff, j.B, 0, d.K * d.N};
+    const ScanJob sj{d, p.qatoms[n], p.qntt[n], j.answer_coeff, j.B, 0, d.K * d.N, 0};
     (j.B == 1 ? p.b1 : p.mf).push_back(sj);
   }
 }
@@ -627,7 +597,7 @@ pir_status pir_db_mul(pir_ctx *ctx, const pir_db *db, const uint32_t *query_ntt,
     StageTimer tm(ctx, s, PIR_STAGE_PACK);
     HIP_OR_FAIL(ctx, launch_pack_query(query_ntt, qatoms, B, db->R, db->desc.N, db->desc.K, s));
   }
-  ScanJob job{db->desc, qatoms, query_ntt, answer_ntt, B, 0, db->desc.K * db->desc.N};
+  ScanJob job{db->desc, qatoms, query_ntt, answer_ntt, B, 0, db->desc.K * db->desc.N, 0};
   {
     StageTimer tm(ctx, s, PIR_STAGE_SCAN);
     HIP_OR_FAIL(ctx, run_scan(ctx, job, s));
@@ -758,7 +728,7 @@ pir_status pir_tune(pir_ctx *ctx, const pir_db *db, uint32_t B, pir_stream strea
   uint8_t *base = (uint8_t *)ctx->ws;
   // Timing does not depend on values; start from a defined state all the same.
   HIP_OR_FAIL(ctx, hipMemsetAsync(base, 0, qb + ab + ob, s));
-  ScanJob job{d, base + qb, (const uint32_t *)base, (uint32_t *)(base + qb + ab), B, 0, d.K * d.N};
+  ScanJob job{d, base + qb, (const uint32_t *)base, (uint32_t *)(base + qb + ab), B, 0, d.K * d.N, 0};
   const std::vector<ScanCfg> cands = scan_candidates(B);
   hipEvent_t e0, e1;
   HIP_OR_FAIL(ctx, hipEventCreate(&e0));

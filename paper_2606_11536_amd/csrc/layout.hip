@@ -130,7 +130,55 @@ __global__ __launch_bounds__(256) void k_pack_query(const uint32_t *__restrict__
   }
 }
 
+// One query [R][2][K][N] into columns 2*col_slot + comp of the query atoms:
+// thread = (k, t, ib, half, comp, b) writes the 16 bytes of lane
+// 32*half + 4*cc + b, cc = (2*col_slot + comp) % 8, in atom (k, t, ib, cb).
+__global__ __launch_bounds__(256) void k_pack_query_slot(const uint32_t *__restrict__ q,
+                                                         uint8_t *__restrict__ qatoms,
+                                                         uint32_t col_slot, uint32_t n_cb,
+                                                         uint32_t R, uint32_t N, uint32_t K,
+                                                         uint32_t n_ib) {
+  const size_t total = (size_t)K * N * n_ib * 16;
+  const size_t idx = blockIdx.x * (size_t)blockDim.x + threadIdx.x;
+  if (idx >= total) return;
+  // t fastest, so consecutive threads read consecutive residues
+  const uint32_t t = idx % N;
+  size_t rest = idx / N;
+  const uint32_t sub = rest % 16;
+  rest /= 16;
+  const uint32_t ib = rest % n_ib;
+  const uint32_t k = rest / n_ib;
+  const uint32_t half = sub >> 3, comp = (sub >> 2) & 1, b = sub & 3;
+  const uint32_t col = 2 * col_slot + comp, cb = col / 8, cc = col % 8;
+  uint32_t word[4];
+#pragma unroll
+  for (int q4 = 0; q4 < 4; ++q4) {
+    uint32_t acc = 0;
+#pragma unroll
+    for (int e = 0; e < 4; ++e) {
+      const uint32_t i = ib * 32 + half * 16 + 4 * q4 + e;
+      const uint32_t v = i < R ? q[(((size_t)i * 2 + comp) * K + k) * N + t] : 0u;
+      acc |= ((v >> (7 * b)) & 127u) << (8 * e);
+    }
+    word[q4] = acc;
+  }
+  const size_t atom = (((size_t)k * N + t) * n_ib + ib) * n_cb + cb;
+  reinterpret_cast<uint4 *>(qatoms)[atom * 64 + half * 32 + cc * 4 + b] =
+      make_uint4(word[0], word[1], word[2], word[3]);
+}
+
 }  // namespace
+
+hipError_t launch_pack_query_slot(const uint32_t *q_ntt, uint8_t *qatoms, uint32_t col_slot,
+                                  uint32_t n_cb, uint32_t R, uint32_t N, uint32_t K,
+                                  hipStream_t s) {
+  if (2 * col_slot + 1 >= n_cb * kCB) return hipErrorInvalidValue;
+  const uint32_t n_ib = r_pad(R) / kIB;
+  const size_t total = (size_t)K * N * n_ib * 16;
+  k_pack_query_slot<<<(unsigned)((total + 255) / 256), 256, 0, s>>>(q_ntt, qatoms, col_slot, n_cb,
+                                                                   R, N, K, n_ib);
+  return hipGetLastError();
+}
 
 hipError_t launch_pack_db(const uint32_t *ntt_slab, uint8_t *atoms, uint32_t i0, uint32_t S,
                           uint32_t R, uint32_t C, uint32_t N, uint32_t K, hipStream_t s) {

@@ -89,6 +89,11 @@ hipError_t launch_read_db(const DbDesc &db, uint32_t i0, uint32_t ni, uint32_t j
 // Pack NTT-form queries [B][R][2][K][N] into query atoms (R_pad rows).
 hipError_t launch_pack_query(const uint32_t *q_ntt, uint8_t *qatoms, uint32_t B, uint32_t R,
                              uint32_t N, uint32_t K, hipStream_t s);
+// Pack one NTT-form query [R][2][K][N] into columns 2*col_slot, 2*col_slot+1
+// of query atoms with n_cb column blocks, touching no other column's bytes.
+hipError_t launch_pack_query_slot(const uint32_t *q_ntt, uint8_t *qatoms, uint32_t col_slot,
+                                  uint32_t n_cb, uint32_t R, uint32_t N, uint32_t K,
+                                  hipStream_t s);
 
 // One scan job for the scan kernels: the slots [slot0, slot0 + n_slots) of
 // the flat slot index k * N + t (all K*N slots for a whole scan).
@@ -99,6 +104,7 @@ struct ScanJob {
   uint32_t *out;           // answer NTT form [B][C][2][K][N]
   uint32_t B;
   uint32_t slot0, n_slots;
+  uint32_t cb_stride;      // column blocks per (k, t, ib) in qatoms; 0 = ceil(2B/8)
 };
 
 // A scan kernel variant.  kind 0: batch-1 streaming kernel (jbw row blocks per
@@ -112,6 +118,8 @@ struct ScanCfg {
 
 std::vector<ScanCfg> scan_candidates(uint32_t B);
 ScanCfg scan_default(uint32_t B);
+// Default batched-kernel (kind 1) variant for B columns pairs, including B = 1.
+ScanCfg scan_default_mfma(uint32_t B);
 // Scan every job with one variant; jobs are fused into launches of up to 8.
 // kind 0 needs B == 1 for every job, kind 1 any B (query atoms).
 hipError_t launch_scan(const ScanJob *jobs, size_t n, const ScanCfg &cfg, hipStream_t s);

@@ -207,9 +207,9 @@ constexpr uint32_t kKCB = 4;  // contraction atoms per staged query chunk
 
 struct MfJob {
   DbDesc db;
-  const uint8_t *qatoms;  // query atoms [K][N][n_ib][n_cb]
+  const uint8_t *qatoms;  // query atoms [K][N][n_ib][cb_stride]
   uint32_t *out;          // answer [B][C][2][K][N]
-  uint32_t B, n_cb;
+  uint32_t B, n_cb, cb_stride;
   uint32_t slot0, n_slots, n_jg, n_cbt;  // job's logical blocks = n_slots * n_jg * n_cbt
   uint32_t first;
 };
@@ -244,7 +244,7 @@ __global__ __launch_bounds__(256, OCC) void k_scan_mfma(const MfArgs args) {
   const DevPrime &P = db.primes[k];
   const uint32_t q = P.q;
   const uint32_t tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
-  const uint32_t n_ib = db.n_ib, n_jb = db.n_jb, n_cb = a.n_cb;
+  const uint32_t n_ib = db.n_ib, n_jb = db.n_jb, n_cb = a.n_cb, cbs = a.cb_stride;
   const uint32_t cb0 = cbt * CBW;
   const uint32_t ncb = min((uint32_t)CBW, n_cb - cb0);
 
@@ -259,7 +259,7 @@ __global__ __launch_bounds__(256, OCC) void k_scan_mfma(const MfArgs args) {
     // rows past C read row block 0: valid memory, results discarded
     arow[w] = slot_atoms + (size_t)(jv[w] ? jbs[w] : 0) * n_ib * kAtomBytes;
   }
-  const uint4 *qsrc = reinterpret_cast<const uint4 *>(a.qatoms) + (size_t)slot * n_ib * n_cb * 64;
+  const uint4 *qsrc = reinterpret_cast<const uint4 *>(a.qatoms) + (size_t)slot * n_ib * cbs * 64;
   const uint32_t last = n_ib - 1;
   auto a_load = [&](int w, uint32_t ks) {
     return __builtin_nontemporal_load(
@@ -272,7 +272,7 @@ __global__ __launch_bounds__(256, OCC) void k_scan_mfma(const MfArgs args) {
       const uint32_t kk = idx / (CBW * 64), c = (idx / 64) % CBW, l = idx & 63;
       st[r] = make_uint4(0, 0, 0, 0);
       if (idx < kBuf && ks0 + kk < n_ib && c < ncb)
-        st[r] = qsrc[((size_t)(ks0 + kk) * n_cb + cb0 + c) * 64 + l];
+        st[r] = qsrc[((size_t)(ks0 + kk) * cbs + cb0 + c) * 64 + l];
     }
   };
   auto stage_store = [&](uint4 *buf, const uint4 (&st)[kPer]) {
@@ -407,6 +407,7 @@ hipError_t run_mfma(const ScanJob *jobs, size_t n, hipStream_t s) {
     m.out = job.out;
     m.B = job.B;
     m.n_cb = (2 * job.B + kCB - 1) / kCB;
+    m.cb_stride = job.cb_stride ? job.cb_stride : m.n_cb;
     m.slot0 = job.slot0;
     m.n_slots = job.n_slots;
     m.n_jg = (job.db.n_jb + 4 * JBW - 1) / (4 * JBW);
@@ -464,6 +465,12 @@ std::vector<ScanCfg> scan_candidates(uint32_t B) {
   return out;
 }
 
+ScanCfg scan_default_mfma(uint32_t B) {
+  const uint32_t cbw = cbw_for(B);
+  const uint8_t lg = cbw == 8 ? 3 : cbw == 4 ? 2 : cbw == 2 ? 1 : 0;
+  return ScanCfg{1, 2, 8, lg};
+}
+
 ScanCfg scan_default(uint32_t B) {
   if (B == 1) return ScanCfg{0, 2, 8, 1};
   const uint32_t cbw = cbw_for(B);
@@ -476,6 +483,7 @@ hipError_t launch_scan(const ScanJob *jobs, size_t n, const ScanCfg &cfg, hipStr
     const ScanJob &j = jobs[i];
     if ((cfg.kind == 0) != (j.B == 1)) return hipErrorInvalidValue;
     if (j.n_slots == 0 || j.slot0 + j.n_slots > j.db.K * j.db.N) return hipErrorInvalidValue;
+    if (j.cb_stride && j.cb_stride * kCB < 2 * j.B) return hipErrorInvalidValue;
   }
   for (const Variant &v : kVariants) {
     if (v.cfg.kind != cfg.kind || v.cfg.jbw != cfg.jbw || v.cfg.unr != cfg.unr || v.cfg.nt != cfg.nt)

@@ -66,6 +66,12 @@ SIGNATURES = {
     "pir_tune": (ct.c_int, [_P, _P, _U32, _P, ct.c_char_p, ct.c_size_t]),
     "pir_tune_batch": (ct.c_int, [_P, ct.POINTER(CJob), ct.c_size_t, _P, ct.c_char_p,
                                   ct.c_size_t]),
+    "pir_server_create": (ct.c_int, [_P, _P, _U32, _U32, ct.POINTER(ct.c_void_p)]),
+    "pir_server_destroy": (None, [_P]),
+    "pir_server_submit": (ct.c_int, [_P, _P, _P, ct.POINTER(ct.c_uint64)]),
+    "pir_server_step": (ct.c_int, [_P, _P, _U32P, _U32P]),
+    "pir_server_poll": (ct.c_int, [_P, ct.c_uint64, ct.POINTER(ct.c_int)]),
+    "pir_server_info": (ct.c_int, [_P, _U32P, _U32P, _U32P, _U32P]),
     "pir_profile_enable": (ct.c_int, [_P, ct.c_int]),
     "pir_profile_read": (ct.c_int, [_P, _U32, ct.POINTER(ct.c_double),
                                     ct.POINTER(ct.c_uint64)]),
@@ -195,10 +201,13 @@ class Context:
         _check(lib.pir_ctx_create(device, hbm_budget_bytes, ct.byref(h)))
         self.handle, self.device = h, device
         self._dbs = weakref.WeakSet()
+        self._servers = weakref.WeakSet()
 
     def close(self) -> None:
         """Free this context's databases, then the context."""
         if self.handle:
+            for srv in list(self._servers):
+                srv.close()
             for db in list(self._dbs):
                 db.free()
             lib.pir_ctx_destroy(self.handle)
@@ -303,3 +312,52 @@ class Context:
 
 def scan_variants(B: int) -> int:
     return lib.pir_scan_variants(B)
+
+
+class Server:
+    """Continuous-batching server over one database (see pir_server_* in pir.h)."""
+
+    def __init__(self, ctx: Context, db: Database, max_batch: int, n_chunks: int):
+        h = ct.c_void_p()
+        self.handle = None
+        _check(lib.pir_server_create(ctx.handle, db.handle, max_batch, n_chunks, ct.byref(h)),
+               ctx.handle)
+        self.handle, self.ctx, self.db = h, ctx, db
+        self._keep = {}
+        ctx._servers.add(self)
+
+    def close(self) -> None:
+        if self.handle and self.ctx.handle:
+            lib.pir_server_destroy(self.handle)
+        self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def submit(self, query_coeff, answer_coeff) -> int:
+        t = ct.c_uint64()
+        _check(lib.pir_server_submit(self.handle, _ptr(query_coeff), _ptr(answer_coeff),
+                                     ct.byref(t)), self.ctx.handle)
+        self._keep[t.value] = (query_coeff, answer_coeff)
+        return t.value
+
+    def step(self, stream=None) -> tuple[int, int]:
+        a, f = ct.c_uint32(), ct.c_uint32()
+        _check(lib.pir_server_step(self.handle, _stream(stream), ct.byref(a), ct.byref(f)),
+               self.ctx.handle)
+        return a.value, f.value
+
+    def poll(self, ticket: int) -> bool:
+        d = ct.c_int()
+        _check(lib.pir_server_poll(self.handle, ticket, ct.byref(d)), self.ctx.handle)
+        if d.value:
+            self._keep.pop(ticket, None)
+        return bool(d.value)
+
+    def info(self) -> dict:
+        v = [ct.c_uint32() for _ in range(4)]
+        _check(lib.pir_server_info(self.handle, *[ct.byref(x) for x in v]), self.ctx.handle)
+        return dict(zip(["max_batch", "active", "queued", "next_chunk"], [x.value for x in v]))
