@@ -178,6 +178,20 @@ typedef struct {
 pir_status pir_answer_batch(pir_ctx *ctx, const pir_job *jobs, size_t n_jobs,
                             pir_stream stream);
 
+/* ---- a5 steady state: a job list captured once into a HIP graph.
+ * pir_plan_create records what pir_answer_batch(jobs) enqueues (all kernel
+ * launches, with the scan variants chosen at that moment) into a graph with
+ * a workspace of its own; pir_plan_launch replays it on `stream` with no
+ * host-side decoding.  The buffers named by the jobs are baked in: refill the
+ * query buffers between launches to answer new queries.  The jobs' databases
+ * must outlive the plan.  pir_plan_destroy waits for the device. */
+typedef struct pir_plan pir_plan;
+
+pir_status pir_plan_create(pir_ctx *ctx, const pir_job *jobs, size_t n_jobs, pir_stream stream,
+                           pir_plan **out);
+pir_status pir_plan_launch(pir_plan *plan, pir_stream stream);
+void pir_plan_destroy(pir_plan *plan);
+
 /* ---- tuning of the scan (a3).  Several kernel variants compute the same
  * exact result with different tile shapes, unroll depths and load policies.
  * The context remembers one variant per (N, K, R, C, B); without a choice a

@@ -605,19 +605,15 @@ pir_status pir_db_mul(pir_ctx *ctx, const pir_db *db, const uint32_t *query_ntt,
   return PIR_OK;
 }
 
-pir_status pir_answer_batch(pir_ctx *ctx, const pir_job *jobs, size_t n_jobs, pir_stream stream) {
-  if (!ctx) return PIR_ERR_INVALID_ARG;
-  if (!jobs && n_jobs) return fail(ctx, PIR_ERR_INVALID_ARG, "jobs is NULL");
-  // Workspace: one shared region for the NTT-form queries of batched jobs
-  // (consumed by their pack before the next job's NTT), a region of its own
-  // for each batch-1 job (read by its scan), and the query atoms of every job.
-  BatchPlan p;
-  pir_status st = plan_batch(ctx, jobs, n_jobs, p);
-  if (st != PIR_OK || n_jobs == 0) return st;
-  DeviceGuard g(ctx->device);
-  if ((st = ensure_ws(ctx, p.bytes())) != PIR_OK) return st;
-  hipStream_t s = (hipStream_t)stream;
-  place_batch(jobs, n_jobs, (uint8_t *)ctx->ws, p);
+}  // extern "C"
+
+namespace {
+
+// Enqueue the whole batch (NTT, packing, fused scans, INTT) on `s` using the
+// workspace at `ws` (at least p.bytes()).
+pir_status enqueue_batch(pir_ctx *ctx, const pir_job *jobs, size_t n_jobs, uint8_t *ws,
+                         BatchPlan &p, hipStream_t s) {
+  place_batch(jobs, n_jobs, ws, p);
   for (size_t n = 0; n < n_jobs; ++n) {
     const pir_job &j = jobs[n];
     const DbDesc &d = j.db->desc;
@@ -644,6 +640,95 @@ pir_status pir_answer_batch(pir_ctx *ctx, const pir_job *jobs, size_t n_jobs, pi
                                 d.log2n, d.primes, true, s));
   }
   return PIR_OK;
+}
+
+}  // namespace
+
+struct pir_plan {
+  pir_ctx *ctx = nullptr;
+  void *ws = nullptr;
+  size_t ws_bytes = 0;
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+};
+
+extern "C" {
+
+pir_status pir_answer_batch(pir_ctx *ctx, const pir_job *jobs, size_t n_jobs, pir_stream stream) {
+  if (!ctx) return PIR_ERR_INVALID_ARG;
+  if (!jobs && n_jobs) return fail(ctx, PIR_ERR_INVALID_ARG, "jobs is NULL");
+  // Workspace: one shared region for the NTT-form queries of batched jobs
+  // (consumed by their pack before the next job's NTT), a region of its own
+  // for each batch-1 job (read by its scan), and the query atoms of every job.
+  BatchPlan p;
+  pir_status st = plan_batch(ctx, jobs, n_jobs, p);
+  if (st != PIR_OK || n_jobs == 0) return st;
+  DeviceGuard g(ctx->device);
+  if ((st = ensure_ws(ctx, p.bytes())) != PIR_OK) return st;
+  return enqueue_batch(ctx, jobs, n_jobs, (uint8_t *)ctx->ws, p, (hipStream_t)stream);
+}
+
+pir_status pir_plan_create(pir_ctx *ctx, const pir_job *jobs, size_t n_jobs, pir_stream stream,
+                           pir_plan **out) {
+  if (!ctx || !out) return PIR_ERR_INVALID_ARG;
+  *out = nullptr;
+  if (!jobs || n_jobs == 0) return fail(ctx, PIR_ERR_INVALID_ARG, "no jobs");
+  BatchPlan p;
+  pir_status st = plan_batch(ctx, jobs, n_jobs, p);
+  if (st != PIR_OK) return st;
+  DeviceGuard g(ctx->device);
+  pir_plan *pl = new (std::nothrow) pir_plan;
+  if (!pl) return fail(ctx, PIR_ERR_OUT_OF_MEMORY, "host allocation failed");
+  pl->ctx = ctx;
+  pl->ws_bytes = std::max<size_t>(p.bytes(), 256);
+  auto bail = [&](pir_status code) {
+    if (pl->exec) (void)hipGraphExecDestroy(pl->exec);
+    if (pl->graph) (void)hipGraphDestroy(pl->graph);
+    dev_free(ctx, pl->ws, pl->ws_bytes);
+    delete pl;
+    return code;
+  };
+  if ((st = dev_alloc(ctx, &pl->ws, pl->ws_bytes, "plan workspace")) != PIR_OK) return bail(st);
+  // Capture on a private stream (kernel launches only; no timing events).
+  hipStream_t cs;
+  if (hipStreamCreateWithFlags(&cs, hipStreamNonBlocking) != hipSuccess)
+    return bail(fail(ctx, PIR_ERR_DEVICE, "hipStreamCreate failed"));
+  const bool prof = ctx->prof;
+  ctx->prof = false;
+  hipError_t e = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal);
+  pir_status qst = PIR_OK;
+  if (e == hipSuccess) qst = enqueue_batch(ctx, jobs, n_jobs, (uint8_t *)pl->ws, p, cs);
+  hipGraph_t graph = nullptr;
+  const hipError_t e2 = e == hipSuccess ? hipStreamEndCapture(cs, &graph) : e;
+  ctx->prof = prof;
+  (void)hipStreamDestroy(cs);
+  pl->graph = graph;
+  if (qst != PIR_OK) return bail(qst);
+  if (e != hipSuccess || e2 != hipSuccess || !graph)
+    return bail(fail(ctx, PIR_ERR_DEVICE, "graph capture failed: %s",
+                     hipGetErrorString(e != hipSuccess ? e : e2)));
+  if ((e = hipGraphInstantiate(&pl->exec, graph, nullptr, nullptr, 0)) != hipSuccess)
+    return bail(fail(ctx, PIR_ERR_DEVICE, "hipGraphInstantiate: %s", hipGetErrorString(e)));
+  (void)stream;
+  *out = pl;
+  return PIR_OK;
+}
+
+pir_status pir_plan_launch(pir_plan *pl, pir_stream stream) {
+  if (!pl) return PIR_ERR_INVALID_ARG;
+  DeviceGuard g(pl->ctx->device);
+  HIP_OR_FAIL(pl->ctx, hipGraphLaunch(pl->exec, (hipStream_t)stream));
+  return PIR_OK;
+}
+
+void pir_plan_destroy(pir_plan *pl) {
+  if (!pl) return;
+  DeviceGuard g(pl->ctx->device);
+  (void)hipDeviceSynchronize();
+  if (pl->exec) (void)hipGraphExecDestroy(pl->exec);
+  if (pl->graph) (void)hipGraphDestroy(pl->graph);
+  dev_free(pl->ctx, pl->ws, pl->ws_bytes);
+  delete pl;
 }
 
 pir_status pir_tune_batch(pir_ctx *ctx, const pir_job *jobs, size_t n_jobs, pir_stream stream,

@@ -66,6 +66,10 @@ SIGNATURES = {
     "pir_tune": (ct.c_int, [_P, _P, _U32, _P, ct.c_char_p, ct.c_size_t]),
     "pir_tune_batch": (ct.c_int, [_P, ct.POINTER(CJob), ct.c_size_t, _P, ct.c_char_p,
                                   ct.c_size_t]),
+    "pir_plan_create": (ct.c_int, [_P, ct.POINTER(CJob), ct.c_size_t, _P,
+                                   ct.POINTER(ct.c_void_p)]),
+    "pir_plan_launch": (ct.c_int, [_P, _P]),
+    "pir_plan_destroy": (None, [_P]),
     "pir_server_create": (ct.c_int, [_P, _P, _U32, _U32, ct.POINTER(ct.c_void_p)]),
     "pir_server_destroy": (None, [_P]),
     "pir_server_submit": (ct.c_int, [_P, _P, _P, ct.POINTER(ct.c_uint64)]),
@@ -280,6 +284,10 @@ class Context:
         _check(lib.pir_answer_batch(self.handle, self._jobs(jobs), len(jobs), _stream(stream)),
                self.handle)
 
+    def plan(self, jobs, stream=None) -> "Plan":
+        """Capture answer_batch(jobs) into a HIP graph (see pir_plan_create)."""
+        return Plan(self, jobs, stream)
+
     def tune_batch(self, jobs, stream=None) -> str:
         """Autotune the fused scan launches for this job list; returns the report."""
         buf = ct.create_string_buffer(8192)
@@ -361,3 +369,29 @@ class Server:
         v = [ct.c_uint32() for _ in range(4)]
         _check(lib.pir_server_info(self.handle, *[ct.byref(x) for x in v]), self.ctx.handle)
         return dict(zip(["max_batch", "active", "queued", "next_chunk"], [x.value for x in v]))
+
+
+class Plan:
+    """A job list captured into a HIP graph; launch() replays it."""
+
+    def __init__(self, ctx: Context, jobs, stream=None):
+        h = ct.c_void_p()
+        self.handle = None
+        _check(lib.pir_plan_create(ctx.handle, Context._jobs(jobs), len(jobs), _stream(stream),
+                                   ct.byref(h)), ctx.handle)
+        self.handle, self.ctx, self._jobs = h, ctx, list(jobs)
+        ctx._servers.add(self)
+
+    def launch(self, stream=None) -> None:
+        _check(lib.pir_plan_launch(self.handle, _stream(stream)), self.ctx.handle)
+
+    def close(self) -> None:
+        if self.handle and self.ctx.handle:
+            lib.pir_plan_destroy(self.handle)
+        self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

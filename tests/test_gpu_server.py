@@ -98,26 +98,35 @@ def test_single_range_and_one_slot(env):
 
 def test_budget_limits_admission(env):
     pir, ctx, db, rg, raw, queries, expect, sec = env
-    per_q = C * 2 * rg.K * rg.N * 4 + (R + 63) // 64 * 64 * 2 * rg.K * rg.N
-    small = pir.Context(0, hbm_budget_bytes=0)
+    n_ib = (R + 63) // 64 * 2
+    per_cb = rg.K * rg.N * n_ib * 1024            # query limbs of 4 column slots
+    ans = C * 2 * rg.K * rg.N * 4                  # answer state of one slot
+    scratch = R * 2 * rg.K * rg.N * 4              # NTT scratch of one admission
+    need4 = per_cb + 4 * ans + scratch             # a server of 4 slots
+    budget = 1 << 30
+    tight = pir.Context(0, hbm_budget_bytes=budget)
     try:
-        sdb = small.load_db(rg.pir_params(), raw, R, C)
-        held = small.device_bytes
-        small.close()
-        tight = pir.Context(0, hbm_budget_bytes=held + 3 * per_q + R * 2 * rg.K * rg.N * 4)
         tdb = tight.load_db(rg.pir_params(), raw, R, C)
+        mib = 1 << 20
+        tight.reserve((budget - tight.device_bytes - need4 - ans // 2) // mib * mib)
+        assert budget - tight.device_bytes >= need4
         srv = pir.Server(tight, tdb, max_batch=64, n_chunks=3)
-        assert 1 <= srv.info()["max_batch"] < 64
-        got = run(pir, srv, {q: 0 for q in range(5)}, queries, rg)
+        assert srv.info()["max_batch"] == 4
+        got = run(pir, srv, {q: 0 for q in range(6)}, queries, rg)
         for q, a in got.items():
             assert np.array_equal(a, expect[q])
         srv.close()
+        with pytest.raises(pir.PirError) as e:
+            tight.reserve(budget - tight.device_bytes + (64 << 20))
+        assert e.value.status == 4
+    finally:
         tight.close()
-        none = pir.Context(0, hbm_budget_bytes=held + 1024)
+    none = pir.Context(0, hbm_budget_bytes=budget)
+    try:
         ndb = none.load_db(rg.pir_params(), raw, R, C)
+        none.reserve((budget - none.device_bytes - scratch) // (1 << 20) * (1 << 20))
         with pytest.raises(pir.PirError) as e:
             pir.Server(none, ndb, max_batch=4, n_chunks=3)
         assert e.value.status == 4
-        none.close()
     finally:
-        small.close()
+        none.close()
