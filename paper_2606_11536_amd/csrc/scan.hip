@@ -481,7 +481,8 @@ ScanCfg scan_default(uint32_t B) {
 hipError_t launch_scan(const ScanJob *jobs, size_t n, const ScanCfg &cfg, hipStream_t s) {
   for (size_t i = 0; i < n; ++i) {
     const ScanJob &j = jobs[i];
-    if ((cfg.kind == 0) != (j.B == 1)) return hipErrorInvalidValue;
+    // the batch-1 kernel reads the NTT-form query; the batched kernel (any B) atoms
+    if (cfg.kind == 0 ? (j.B != 1 || !j.q_ntt) : !j.qatoms) return hipErrorInvalidValue;
     if (j.n_slots == 0 || j.slot0 + j.n_slots > j.db.K * j.db.N) return hipErrorInvalidValue;
     if (j.cb_stride && j.cb_stride * kCB < 2 * j.B) return hipErrorInvalidValue;
   }
