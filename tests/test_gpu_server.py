@@ -117,7 +117,7 @@ def test_budget_limits_admission(env):
             assert np.array_equal(a, expect[q])
         srv.close()
         with pytest.raises(pir.PirError) as e:
-            tight.reserve(budget - tight.device_bytes + (64 << 20))
+            tight.reserve(budget + (64 << 20))
         assert e.value.status == 4
     finally:
         tight.close()
