@@ -39,6 +39,7 @@ TAG_INDEX = 0x1D
 TAG_UNIFORM = 0xBE
 TAG_SIZES = 0x51
 TAG_FREIVALDS = 0xF5
+TAG_ARRIVALS = 0xA7
 
 SIGMA = 3.2
 ERROR_CLIP = 19
@@ -67,6 +68,45 @@ def db_bytes_into(seed: int, out: np.ndarray, row0: int = 0) -> None:
     _, C, N = out.shape
     for r in range(out.shape[0]):
         out[r] = db_row(seed, row0 + r, C, N)
+
+
+def db_bytes_parallel(seed: int, R: int, C: int, N: int, workers: int = 16,
+                      out: np.ndarray | None = None) -> np.ndarray:
+    """``db_bytes`` for large databases: rows drawn on a thread pool (same bytes)."""
+    from concurrent.futures import ThreadPoolExecutor
+    out = np.empty((R, C, N), dtype=np.uint8) if out is None else out
+
+    def fill(i0: int) -> None:
+        for i in range(i0, min(R, i0 + 16)):
+            out[i] = db_row(seed, i, C, N)
+
+    with ThreadPoolExecutor(max_workers=workers) as ex:
+        list(ex.map(fill, range(0, R, 16)))
+    return out
+
+
+def uniform_query_parallel(seed: int, b: int, R: int, primes: list[int], N: int,
+                           workers: int = 16) -> np.ndarray:
+    """``uniform_query`` drawn on a thread pool (same values)."""
+    from concurrent.futures import ThreadPoolExecutor
+    K = len(primes)
+    out = np.empty((R, 2, K, N), dtype=np.uint32)
+
+    def fill(i0: int) -> None:
+        for i in range(i0, min(R, i0 + 64)):
+            g = _rng(seed, TAG_UNIFORM, b, i)
+            for c in range(2):
+                for k, q in enumerate(primes):
+                    out[i, c, k] = g.integers(0, q, size=N, dtype=np.uint32)
+
+    with ThreadPoolExecutor(max_workers=workers) as ex:
+        list(ex.map(fill, range(0, R, 64)))
+    return out
+
+
+def poisson_arrivals(seed: int, rate: float, count: int) -> np.ndarray:
+    """Arrival times (s) of ``count`` requests of a Poisson process of ``rate``/s."""
+    return np.cumsum(_rng(seed, TAG_ARRIVALS, int(rate * 1000)).exponential(1.0 / rate, size=count))
 
 
 def secret(seed: int, b: int, N: int) -> np.ndarray:
