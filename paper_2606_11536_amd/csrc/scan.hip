@@ -69,14 +69,30 @@ __device__ __forceinline__ uint32_t find_job(const Args &a, uint32_t L) {
   return jid;
 }
 
-// Reduce the lane's partial sum s over the 4 lanes b = 0..3 (lane bits 0,1).
+// Reduce the lane's partial sum s over the 4 lanes b = 0..3 (lane bits 0,1)
+// with quad permutes (DPP quad_perm [1,0,3,2] then [2,3,0,1]).
 // Input s in [0, 2q); output in [0, q).
 __device__ __forceinline__ uint32_t quad_sum_mod(uint32_t s, uint32_t q) {
-  s += __shfl_xor(s, 1);  // < 4q
-  s += __shfl_xor(s, 2);  // < 8q
+  s += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)s, 0xB1, 0xF, 0xF, false);  // < 4q
+  s += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)s, 0x4E, 0xF, 0xF, false);  // < 8q
   s = csub(s, 4 * q);
   s = csub(s, 2 * q);
   return csub(s, q);
+}
+
+// sum_a P[a] * 2^(7a) mod q for the four limb sums P[a] < 2^31 of one lane.
+// The sum T is exact in 64 bits (< 2^53) and exactly representable as a
+// double, so a double quotient estimate is off by at most one; the int32
+// remainder T - qhat*q then lies in (-q, 2q) and two corrections make it exact.
+__device__ __forceinline__ uint32_t limb_sum_mod(uint32_t p0, uint32_t p1, uint32_t p2, uint32_t p3,
+                                                 uint32_t q, double inv_q) {
+  const uint64_t T = (uint64_t)p0 + ((uint64_t)p1 << 7) + ((uint64_t)p2 << 14) +
+                     ((uint64_t)p3 << 21);
+  const uint32_t qhat = (uint32_t)((double)T * inv_q);
+  int32_t r = (int32_t)((uint32_t)T - qhat * q);
+  r += r < 0 ? (int32_t)q : 0;
+  r -= r >= (int32_t)q ? (int32_t)q : 0;
+  return (uint32_t)r;
 }
 
 template <bool NT>
@@ -177,12 +193,8 @@ __global__ __launch_bounds__(256) void k_scan_b1(const B1Args args) {
   // Epilogue.  Lane holds rows 4*(lane>>4) + r (row = 4 jl' + a, a = r) of
   // column lane & 15 (= 4 cc + b).
   const uint32_t b = lane & 3, cc = (lane >> 2) & 3, jlp = lane >> 4;
-  uint32_t wv[4], wsh[4];
-#pragma unroll
-  for (int r = 0; r < 4; ++r) {
-    wv[r] = P.w[r + b];
-    wsh[r] = P.w_sh[r + b];
-  }
+  const uint32_t wb = P.w[b], wbsh = P.w_sh[b];
+  const double inv_q = 1.0 / (double)q;
   const size_t KN = (size_t)db.K * db.N;
 #pragma unroll
   for (int w = 0; w < JBW; ++w) {
@@ -190,12 +202,9 @@ __global__ __launch_bounds__(256) void k_scan_b1(const B1Args args) {
     if (jb >= jb_end) break;
 #pragma unroll
     for (int jh = 0; jh < 2; ++jh) {
-      uint32_t s = 0;
-#pragma unroll
-      for (int r = 0; r < 4; ++r) s += mul_shoup((uint32_t)acc[w][jh][r], wv[r], wsh[r], q);
-      s = csub(s, 4 * q);
-      s = csub(s, 2 * q);
-      s = quad_sum_mod(s, q);
+      const v4i &A = acc[w][jh];
+      const uint32_t u = limb_sum_mod(A[0], A[1], A[2], A[3], q, inv_q);
+      const uint32_t s = quad_sum_mod(mul_shoup(u, wb, wbsh, q), q);
       const uint32_t j = jb * 8 + jh * 4 + jlp;
       if (b == 0 && cc < 2 && j < db.C) a.out[((size_t)j * 2 + cc) * KN + (size_t)k * db.N + t] = s;
     }
@@ -210,7 +219,8 @@ struct MfJob {
   const uint8_t *qatoms;  // query atoms [K][N][n_ib][cb_stride]
   uint32_t *out;          // answer [B][C][2][K][N]
   uint32_t B, n_cb, cb_stride;
-  uint32_t slot0, n_slots, n_jg, n_cbt;  // job's logical blocks = n_slots * n_jg * n_cbt
+  uint32_t slot0, n_slots, n_jg, n_cbt;
+  uint32_t ns, n_sg;      // slots per block, slot groups: logical blocks = n_sg * n_jg * n_cbt
   uint32_t first;
 };
 
@@ -220,10 +230,13 @@ struct MfArgs {
 };
 
 // JBW database row blocks x CBW query column blocks per wave; the four waves of
-// a block take consecutive row blocks.  D = depth of the database-atom ring:
-// the atoms of contraction step ks + D are requested while step ks computes.
-// Steps past the end read a clamped (valid) atom and meet zero query atoms, so
-// the loop has no data-dependent branch and the load counters stay exact.
+// a block take consecutive row blocks of one slot.  The slot takes S steps
+// (n_ib rounded up to the ring depth D; steps past n_ib meet zero query atoms
+// and read valid padding memory); the database-atom ring requests step g + D
+// while step g computes, and query atoms come through double-buffered LDS
+// chunks of kKCB steps.  No load sits under a data-dependent branch, so the
+// load counters stay exact.  (MfJob::ns > 1 is reserved for streaming several
+// slots per block; the launcher sets 1.)
 template <int JBW, int CBW, int D, int OCC>
 __global__ __launch_bounds__(256, OCC) void k_scan_mfma(const MfArgs args) {
   static_assert(D % kKCB == 0, "ring depth must be a multiple of the query chunk");
@@ -235,50 +248,68 @@ __global__ __launch_bounds__(256, OCC) void k_scan_mfma(const MfArgs args) {
   const MfJob &a = args.jobs[find_job(args, Lg)];
   const uint32_t L = Lg - a.first;
   const DbDesc &db = a.db;
-  // column tiles of the same rows are adjacent, then row groups of one slot:
-  // a database atom's second read and a slot's query atoms come from L2
+  // column tiles of the same rows are adjacent, then row groups of one slot
+  // group: a database atom's second read and a slot's query atoms hit L2
   const uint32_t cbt = L % a.n_cbt;
   const uint32_t rest = L / a.n_cbt;
-  const uint32_t jg = rest % a.n_jg, slot = a.slot0 + rest / a.n_jg;
-  const uint32_t k = slot >> db.log2n, t = slot & (db.N - 1);
-  const DevPrime &P = db.primes[k];
-  const uint32_t q = P.q;
-  const uint32_t tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
+  const uint32_t jg = rest % a.n_jg, sg = rest / a.n_jg;
+  const uint32_t s_begin = a.slot0 + sg * a.ns;
+  const uint32_t s_count = min(a.ns, a.slot0 + a.n_slots - s_begin);
+  const uint32_t tid = threadIdx.x, lane = tid & 63;
+  const uint32_t wave = __builtin_amdgcn_readfirstlane(tid >> 6);
   const uint32_t n_ib = db.n_ib, n_jb = db.n_jb, n_cb = a.n_cb, cbs = a.cb_stride;
   const uint32_t cb0 = cbt * CBW;
   const uint32_t ncb = min((uint32_t)CBW, n_cb - cb0);
+  const uint32_t S = (n_ib + D - 1) / D * D;  // steps per slot
 
   uint32_t jbs[JBW];
   bool jv[JBW];
-  const uint8_t *arow[JBW];
-  const uint8_t *slot_atoms = db.atoms + (size_t)slot * n_jb * n_ib * kAtomBytes + lane * 16;
+  size_t row_off[JBW];
 #pragma unroll
   for (int w = 0; w < JBW; ++w) {
     jbs[w] = (jg * 4 + wave) * JBW + w;
     jv[w] = jbs[w] < n_jb;
     // rows past C read row block 0: valid memory, results discarded
-    arow[w] = slot_atoms + (size_t)(jv[w] ? jbs[w] : 0) * n_ib * kAtomBytes;
+    row_off[w] = (size_t)(jv[w] ? jbs[w] : 0) * n_ib * kAtomBytes;
   }
-  const uint4 *qsrc = reinterpret_cast<const uint4 *>(a.qatoms) + (size_t)slot * n_ib * cbs * 64;
-  const uint32_t last = n_ib - 1;
-  auto a_load = [&](int w, uint32_t ks) {
-    return __builtin_nontemporal_load(
-        reinterpret_cast<const v4i *>(arow[w] + (size_t)min(ks, last) * kAtomBytes));
+  const size_t slot_stride = (size_t)n_jb * n_ib * kAtomBytes;
+  const uint8_t *atoms_lane = db.atoms + lane * 16;
+  // First atom of ring group (u, ks) for row block w; groups past the block
+  // read the block's first atom (valid memory, never used).  Steps of a slot
+  // past n_ib run into the following atoms or the allocation's tail padding
+  // and meet zero query atoms.
+  auto group_ptr = [&](int w, uint32_t u, uint32_t ks) {
+    const bool ok = u < s_count;
+    const size_t off = (size_t)(s_begin + (ok ? u : 0)) * slot_stride + row_off[w] +
+                       (size_t)(ok ? ks : 0) * kAtomBytes;
+    return atoms_lane + off;
   };
-  auto stage_load = [&](uint32_t ks0, uint4 (&st)[kPer]) {
+  const uint4 *qbase = reinterpret_cast<const uint4 *>(a.qatoms);
+  // query atoms of the chunk starting at step ks of slot u (zero past the block)
+  auto stage_load = [&](uint32_t u, uint32_t ks, uint4 (&st)[kPer]) {
+    const bool uok = u < s_count;
+    const uint4 *qs = qbase + (size_t)(s_begin + (uok ? u : 0)) * n_ib * cbs * 64;
 #pragma unroll
     for (uint32_t r = 0; r < kPer; ++r) {
       const uint32_t idx = tid + 256 * r;
       const uint32_t kk = idx / (CBW * 64), c = (idx / 64) % CBW, l = idx & 63;
-      st[r] = make_uint4(0, 0, 0, 0);
-      if (idx < kBuf && ks0 + kk < n_ib && c < ncb)
-        st[r] = qsrc[((size_t)(ks0 + kk) * cbs + cb0 + c) * 64 + l];
+      const bool ok = uok && idx < kBuf && ks + kk < n_ib && c < ncb;
+      const uint4 v = qs[ok ? ((size_t)(ks + kk) * cbs + cb0 + c) * 64 + l : 0];
+      st[r] = ok ? v : make_uint4(0, 0, 0, 0);
     }
   };
   auto stage_store = [&](uint4 *buf, const uint4 (&st)[kPer]) {
 #pragma unroll
     for (uint32_t r = 0; r < kPer; ++r)
       if (tid + 256 * r < kBuf) buf[tid + 256 * r] = st[r];
+  };
+  v4i bcur[CBW], bnext[CBW];
+  auto b_read = [&](const uint4 *src, v4i (&bv)[CBW]) {
+#pragma unroll
+    for (int c = 0; c < CBW; ++c) {
+      const uint4 u = src[c * 64 + lane];
+      bv[c] = v4i{(int)u.x, (int)u.y, (int)u.z, (int)u.w};
+    }
   };
 
   v16i acc[JBW][CBW];
@@ -289,82 +320,93 @@ __global__ __launch_bounds__(256, OCC) void k_scan_mfma(const MfArgs args) {
 
   v4i ring[D][JBW];
 #pragma unroll
-  for (int d = 0; d < D; ++d)
+  for (int w = 0; w < JBW; ++w) {
+    const uint8_t *p = group_ptr(w, 0, 0);
 #pragma unroll
-    for (int w = 0; w < JBW; ++w) ring[d][w] = a_load(w, d);
+    for (int d = 0; d < D; ++d)
+      ring[d][w] = __builtin_nontemporal_load(reinterpret_cast<const v4i *>(p + d * kAtomBytes));
+  }
   uint4 st[kPer];
-  stage_load(0, st);
+  stage_load(0, 0, st);
   stage_store(sq, st);
   __syncthreads();
-
-  // Query operands of the current step; those of the next step are read from
-  // LDS while the current step's MFMAs run (within a chunk; across a chunk
-  // boundary they are read right after the barrier that publishes the chunk).
-  v4i bcur[CBW], bnext[CBW];
-  auto b_read = [&](const uint4 *src, v4i (&bv)[CBW]) {
-#pragma unroll
-    for (int c = 0; c < CBW; ++c) {
-      const uint4 u = src[c * 64 + lane];
-      bv[c] = v4i{(int)u.x, (int)u.y, (int)u.z, (int)u.w};
-    }
-  };
   b_read(sq, bcur);
-  const uint32_t n_steps = (n_ib + D - 1) / D * D;
-  for (uint32_t ks0 = 0; ks0 < n_steps; ks0 += D) {
-#pragma unroll
-    for (int d = 0; d < D; ++d) {
-      const uint32_t ks = ks0 + d;
-      const uint32_t chunk = ks / kKCB;
-      const int kk = d % kKCB;
-      if (kk == 0) stage_load(ks + kKCB, st);  // next chunk, in flight during this one
-      if (kk + 1 < (int)kKCB) b_read(sq + (chunk & 1) * kBuf + (kk + 1) * CBW * 64, bnext);
-#pragma unroll
-      for (int c = 0; c < CBW; ++c)
-#pragma unroll
-        for (int w = 0; w < JBW; ++w)
-          acc[w][c] = __builtin_amdgcn_mfma_i32_32x32x32_i8(ring[d][w], bcur[c], acc[w][c], 0, 0, 0);
-#pragma unroll
-      for (int w = 0; w < JBW; ++w) ring[d][w] = a_load(w, ks + D);
-      if (kk == (int)kKCB - 1) {
-        stage_store(sq + ((chunk + 1) & 1) * kBuf, st);
-        __syncthreads();
-        b_read(sq + ((chunk + 1) & 1) * kBuf, bnext);
-      }
-#pragma unroll
-      for (int c = 0; c < CBW; ++c) bcur[c] = bnext[c];
-    }
-  }
 
-  // Epilogue.  32x32 result: lane holds column lane & 31 (= 4 cc + b) and, in
-  // register r, row 8*(r>>2) + 4*(lane>>5) + (r&3)  (row = 4 jl + a).
+  // epilogue constants.  32x32 result: lane holds column lane & 31 (= 4 cc + b)
+  // and, in register r, row 8*(r>>2) + 4*(lane>>5) + (r&3)  (row = 4 jl + a).
   const uint32_t b = lane & 3, cc = (lane >> 2) & 7, hi = lane >> 5;
-  uint32_t wv[4], wsh[4];
-#pragma unroll
-  for (int r = 0; r < 4; ++r) {
-    wv[r] = P.w[r + b];
-    wsh[r] = P.w_sh[r + b];
-  }
   const size_t KN = (size_t)db.K * db.N;
   const uint32_t ncol = 2 * a.B;
+  uint32_t chunk = 0;  // chunks completed (LDS buffer parity)
+
+  {
+    const uint32_t u = 0;
+    for (uint32_t ks0 = 0; ks0 < S; ks0 += D) {
+      // the group that refills the ring: next D steps of this slot or the next slot
+      const bool same = ks0 + D < S;
+      const uint32_t ur = same ? u : u + 1, kr = same ? ks0 + D : 0;
+      const uint8_t *rp[JBW];
 #pragma unroll
-  for (int w = 0; w < JBW; ++w) {
-    if (!jv[w]) continue;
+      for (int w = 0; w < JBW; ++w) rp[w] = group_ptr(w, ur, kr);
 #pragma unroll
-    for (int c = 0; c < CBW; ++c) {
-      if ((uint32_t)c >= ncb) break;
-      const uint32_t col = (cb0 + c) * 8 + cc;
+      for (int d = 0; d < D; ++d) {
+        const int kk = d % kKCB;
+        if (kk == 0) {
+          // next chunk, in flight during this one
+          if (d + kKCB < D) stage_load(u, ks0 + d + kKCB, st);
+          else stage_load(ur, kr, st);
+        }
+        if (kk + 1 < (int)kKCB) b_read(sq + (chunk & 1) * kBuf + (kk + 1) * CBW * 64, bnext);
 #pragma unroll
-      for (int qq = 0; qq < 4; ++qq) {
-        uint32_t s = 0;
+        for (int c = 0; c < CBW; ++c)
 #pragma unroll
-        for (int r = 0; r < 4; ++r)
-          s += mul_shoup((uint32_t)acc[w][c][4 * qq + r], wv[r], wsh[r], q);
-        s = csub(s, 4 * q);
-        s = csub(s, 2 * q);
-        s = quad_sum_mod(s, q);
-        const uint32_t j = jbs[w] * 8 + 2 * qq + hi;
-        if (b == 0 && j < db.C && col < ncol)
-          a.out[(((size_t)(col >> 1) * db.C + j) * 2 + (col & 1)) * KN + (size_t)k * db.N + t] = s;
+          for (int w = 0; w < JBW; ++w)
+            acc[w][c] = __builtin_amdgcn_mfma_i32_32x32x32_i8(ring[d][w], bcur[c], acc[w][c], 0, 0, 0);
+#pragma unroll
+        for (int w = 0; w < JBW; ++w)
+          ring[d][w] = __builtin_nontemporal_load(reinterpret_cast<const v4i *>(rp[w] + d * kAtomBytes));
+        if (kk == (int)kKCB - 1) {
+          ++chunk;
+          stage_store(sq + (chunk & 1) * kBuf, st);
+          __syncthreads();
+          b_read(sq + (chunk & 1) * kBuf, bnext);
+        }
+#pragma unroll
+        for (int c = 0; c < CBW; ++c) bcur[c] = bnext[c];
+      }
+    }
+  }
+  {
+    // the slot is complete: reduce and store
+    const uint32_t slot = s_begin;
+    const uint32_t k = slot >> db.log2n, t = slot & (db.N - 1);
+    const DevPrime &P = db.primes[k];
+    const uint32_t q = P.q;
+    uint32_t wv[4], wsh[4];
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      wv[r] = P.w[r + b];
+      wsh[r] = P.w_sh[r + b];
+    }
+#pragma unroll
+    for (int w = 0; w < JBW; ++w) {
+#pragma unroll
+      for (int c = 0; c < CBW; ++c) {
+        const uint32_t col = (cb0 + c) * 8 + cc;
+#pragma unroll
+        for (int qq = 0; qq < 4; ++qq) {
+          // sum over limbs a in the lane (Shoup products), then over b across lanes
+          uint32_t s2 = 0;
+#pragma unroll
+          for (int r = 0; r < 4; ++r)
+            s2 += mul_shoup((uint32_t)acc[w][c][4 * qq + r], wv[r], wsh[r], q);
+          s2 = csub(s2, 4 * q);
+          s2 = csub(s2, 2 * q);
+          const uint32_t sv = quad_sum_mod(s2, q);
+          const uint32_t j = jbs[w] * 8 + 2 * qq + hi;
+          if (jv[w] && (uint32_t)c < ncb && b == 0 && j < db.C && col < ncol)
+            a.out[(((size_t)(col >> 1) * db.C + j) * 2 + (col & 1)) * KN + (size_t)k * db.N + t] = sv;
+        }
       }
     }
   }
@@ -412,8 +454,15 @@ hipError_t run_mfma(const ScanJob *jobs, size_t n, hipStream_t s) {
     m.n_slots = job.n_slots;
     m.n_jg = (job.db.n_jb + 4 * JBW - 1) / (4 * JBW);
     m.n_cbt = (m.n_cb + CBW - 1) / CBW;
+    // enough blocks to fill the chip several times over, each streaming up to
+    // 16 slots so that only the first pays the pipeline fill
+    const uint32_t per_slot = m.n_jg * m.n_cbt;
+    (void)per_slot;
+    const uint32_t ns = 1;  // one slot per block
+    m.ns = ns;
+    m.n_sg = (m.n_slots + ns - 1) / ns;
     m.first = total;
-    total += m.n_cbt * m.n_slots * m.n_jg;
+    total += m.n_cbt * m.n_sg * m.n_jg;
   }
   a.n_jobs = (uint32_t)n;
   a.total = total;
