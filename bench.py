@@ -369,7 +369,7 @@ def main() -> int:
         ctx.answer_batch(jobs)
     torch.cuda.synchronize()
     t1 = time.perf_counter()
-    stage = {s: ctx.profile_read(s) for s in ("ntt", "pack", "scan", "intt")}
+    stage = {s: ctx.profile_read(s) for s in ("ntt", "pack", "scan", "unpack", "intt")}
     ctx.profile(False)
     wall = t1 - t0
     ms_per_step = wall * 1e3 / args.steps

@@ -156,8 +156,9 @@ pir_status pir_intt(pir_ctx *ctx, const pir_params *params, uint32_t *polys, siz
  * query_ntt: device [B][R][2][K][N], NTT form; answer_ntt: device
  * [B][C][2][K][N], NTT form, fully overwritten:
  *   answer[b][j][c][k][t] = sum_i D_k[i][j][t] * query[b][i][c][k][t] (mod q_k).
- * 1 <= B <= PIR_MAX_BATCH.  Uses context workspace of about
- * B*R_pad*2*K*N bytes (grown on demand). */
+ * 1 <= B <= PIR_MAX_BATCH.  For B > 1 uses context workspace of about
+ * B*R_pad*2*K*N (query tiles) + B*C*2*K*N*4 (answers in scan order) bytes,
+ * grown on demand. */
 #define PIR_MAX_BATCH 256u
 pir_status pir_db_mul(pir_ctx *ctx, const pir_db *db, const uint32_t *query_ntt, uint32_t B,
                       uint32_t *answer_ntt, pir_stream stream);
@@ -265,7 +266,8 @@ typedef enum {
   PIR_STAGE_PACK = 1, /* query transposition into scan tiles */
   PIR_STAGE_SCAN = 2, /* the database scan */
   PIR_STAGE_INTT = 3, /* inverse NTT of answers */
-  PIR_N_STAGES = 4
+  PIR_STAGE_UNPACK = 4, /* answer transposition out of scan order (B > 1) */
+  PIR_N_STAGES = 5
 } pir_stage;
 
 pir_status pir_profile_enable(pir_ctx *ctx, int enable);

@@ -262,6 +262,9 @@ void profile_drain(pir_ctx *ctx) {
   ctx->pending.clear();
 }
 
+// Answers of B queries: [B][C][2][K][N] words (also the slot-major size).
+size_t answer_bytes(const DbDesc &d, uint32_t B) { return (size_t)B * d.C * 2 * d.K * d.N * 4; }
+
 size_t query_atom_bytes(const DbDesc &d, uint32_t B) {
   if (B == 1) return 0;  // the batch-1 kernel reads the NTT-form query directly
   const uint32_t n_cb = (2 * B + kCB - 1) / kCB;
@@ -306,11 +309,12 @@ ScanCfg group_cfg(const pir_ctx *ctx, const std::vector<ScanJob> &g) {
 
 // Workspace layout and scan jobs of a job list (see pir_answer_batch).
 struct BatchPlan {
-  size_t shared_q = 0, own_q = 0, atoms = 0;
+  size_t shared_q = 0, own_q = 0, atoms = 0, slot_major = 0;
   std::vector<ScanJob> b1, mf;      // fused groups: batch-1 kernel, batched kernel
   std::vector<uint32_t *> qntt;     // per job: where its NTT-form query goes
   std::vector<uint8_t *> qatoms;    // per job: its query atoms (batched kernel)
-  size_t bytes() const { return shared_q + own_q + atoms; }
+  std::vector<uint32_t *> sm;       // per job: its slot-major answers (batched kernel)
+  size_t bytes() const { return shared_q + own_q + atoms + slot_major; }
 };
 
 size_t al256(size_t x) { return (x + 255) & ~(size_t)255; }
@@ -329,6 +333,7 @@ pir_status plan_batch(pir_ctx *ctx, const pir_job *jobs, size_t n_jobs, BatchPla
     if (j.B == 1) p.own_q += qb;
     else p.shared_q = std::max(p.shared_q, qb);
     p.atoms += al256(query_atom_bytes(d, j.B));
+    if (j.B > 1) p.slot_major += al256(answer_bytes(d, j.B));
   }
   return PIR_OK;
 }
@@ -337,8 +342,10 @@ pir_status plan_batch(pir_ctx *ctx, const pir_job *jobs, size_t n_jobs, BatchPla
 void place_batch(const pir_job *jobs, size_t n_jobs, uint8_t *base, BatchPlan &p) {
   uint8_t *own = base + p.shared_q;
   uint8_t *atoms = own + p.own_q;
+  uint8_t *sm = atoms + p.atoms;
   p.qntt.assign(n_jobs, nullptr);
   p.qatoms.assign(n_jobs, nullptr);
+  p.sm.assign(n_jobs, nullptr);
   p.b1.clear();
   p.mf.clear();
   for (size_t n = 0; n < n_jobs; ++n) {
@@ -351,7 +358,12 @@ void place_batch(const pir_job *jobs, size_t n_jobs, uint8_t *base, BatchPlan &p
     }
     p.qatoms[n] = atoms;
     atoms += al256(query_atom_bytes(d, j.B));
-    const ScanJob sj{d, p.qatoms[n], p.qntt[n], j.answer_coeff, j.B, 0, d.K * d.N, 0};
+    if (j.B > 1) {
+      p.sm[n] = (uint32_t *)sm;
+      sm += al256(answer_bytes(d, j.B));
+    }
+    const ScanJob sj{d, p.qatoms[n], p.qntt[n], j.B == 1 ? j.answer_coeff : p.sm[n], j.B, 0,
+                     d.K * d.N, 0, 0};
     (j.B == 1 ? p.b1 : p.mf).push_back(sj);
   }
 }
@@ -590,19 +602,28 @@ pir_status pir_db_mul(pir_ctx *ctx, const pir_db *db, const uint32_t *query_ntt,
   if (db->ctx != ctx) return fail(ctx, PIR_ERR_INVALID_ARG, "database belongs to another context");
   if (B < 1 || B > PIR_MAX_BATCH) return fail(ctx, PIR_ERR_INVALID_ARG, "B=%u out of range", B);
   DeviceGuard g(ctx->device);
-  const size_t qa = query_atom_bytes(db->desc, B);
-  pir_status st = ensure_ws(ctx, qa);
+  const DbDesc &d = db->desc;
+  // B > 1: query atoms, then the slot-major answers of the batched kernel
+  const size_t qa = B > 1 ? al256(query_atom_bytes(d, B)) : 0;
+  const size_t sm = B > 1 ? answer_bytes(d, B) : 0;
+  pir_status st = ensure_ws(ctx, std::max<size_t>(qa + sm, 256));
   if (st != PIR_OK) return st;
   hipStream_t s = (hipStream_t)stream;
   uint8_t *qatoms = (uint8_t *)ctx->ws;
+  uint32_t *slot_major = (uint32_t *)((uint8_t *)ctx->ws + qa);
   if (B > 1) {
     StageTimer tm(ctx, s, PIR_STAGE_PACK);
-    HIP_OR_FAIL(ctx, launch_pack_query(query_ntt, qatoms, B, db->R, db->desc.N, db->desc.K, s));
+    HIP_OR_FAIL(ctx, launch_pack_query(query_ntt, qatoms, B, db->R, d.N, d.K, s));
   }
-  ScanJob job{db->desc, qatoms, query_ntt, answer_ntt, B, 0, db->desc.K * db->desc.N, 0};
+  ScanJob job{d, qatoms, query_ntt, B > 1 ? slot_major : answer_ntt, B, 0, d.K * d.N, 0, 0};
   {
     StageTimer tm(ctx, s, PIR_STAGE_SCAN);
     HIP_OR_FAIL(ctx, run_scan(ctx, job, s));
+  }
+  if (B > 1) {
+    StageTimer tm(ctx, s, PIR_STAGE_UNPACK);
+    const uint32_t P = 2 * B * d.C;
+    HIP_OR_FAIL(ctx, launch_unpack_answers(slot_major, P, 0, P, d.K * d.N, answer_ntt, s));
   }
   return PIR_OK;
 }
@@ -637,6 +658,11 @@ pir_status enqueue_batch(pir_ctx *ctx, const pir_job *jobs, size_t n_jobs, uint8
   }
   for (size_t n = 0; n < n_jobs; ++n) {
     const DbDesc &d = jobs[n].db->desc;
+    if (p.sm[n]) {
+      StageTimer tm(ctx, s, PIR_STAGE_UNPACK);
+      const uint32_t P = 2 * jobs[n].B * d.C;
+      HIP_OR_FAIL(ctx, launch_unpack_answers(p.sm[n], P, 0, P, d.K * d.N, jobs[n].answer_coeff, s));
+    }
     StageTimer tm(ctx, s, PIR_STAGE_INTT);
     HIP_OR_FAIL(ctx, launch_ntt(jobs[n].answer_coeff, (size_t)jobs[n].B * d.C * 2 * d.K, d.K,
                                 d.log2n, d.primes, true, s));
@@ -815,7 +841,8 @@ pir_status pir_tune(pir_ctx *ctx, const pir_db *db, uint32_t B, pir_stream strea
   uint8_t *base = (uint8_t *)ctx->ws;
   // Timing does not depend on values; start from a defined state all the same.
   HIP_OR_FAIL(ctx, hipMemsetAsync(base, 0, qb + ab + ob, s));
-  ScanJob job{d, base + qb, (const uint32_t *)base, (uint32_t *)(base + qb + ab), B, 0, d.K * d.N, 0};
+  ScanJob job{d, base + qb, (const uint32_t *)base, (uint32_t *)(base + qb + ab), B, 0, d.K * d.N, 0,
+              0};
   const std::vector<ScanCfg> cands = scan_candidates(B);
   hipEvent_t e0, e1;
   HIP_OR_FAIL(ctx, hipEventCreate(&e0));

@@ -167,7 +167,37 @@ __global__ __launch_bounds__(256) void k_pack_query_slot(const uint32_t *__restr
       make_uint4(word[0], word[1], word[2], word[3]);
 }
 
+// Slot-major answers -> polynomial-major: out[p][s] = sm[s * p_stride + p0 + p].
+// A block moves a 64 (slots) x 64 (polynomials) tile through LDS, reading and
+// writing 256-byte rows.
+__global__ __launch_bounds__(256) void k_unpack_answers(const uint32_t *__restrict__ sm,
+                                                        uint32_t p_stride, uint32_t p0, uint32_t P,
+                                                        uint32_t KN, uint32_t *__restrict__ out) {
+  __shared__ uint32_t tile[64][65];
+  const uint32_t pb = blockIdx.x * 64, s0 = blockIdx.y * 64;
+  const uint32_t tx = threadIdx.x & 63, ty = threadIdx.x >> 6;
+#pragma unroll 4
+  for (uint32_t r = ty; r < 64; r += 4) {
+    const uint32_t p = pb + tx;
+    tile[r][tx] = p < P ? sm[(size_t)(s0 + r) * p_stride + p0 + p] : 0u;
+  }
+  __syncthreads();
+#pragma unroll 4
+  for (uint32_t r = ty; r < 64; r += 4) {
+    const uint32_t p = pb + r;
+    if (p < P) out[(size_t)p * KN + s0 + tx] = tile[tx][r];
+  }
+}
+
 }  // namespace
+
+hipError_t launch_unpack_answers(const uint32_t *sm, uint32_t p_stride, uint32_t p0, uint32_t P,
+                                 uint32_t KN, uint32_t *out, hipStream_t s) {
+  if (KN % 64 != 0 || (size_t)p0 + P > p_stride) return hipErrorInvalidValue;
+  if (P == 0) return hipSuccess;
+  k_unpack_answers<<<dim3((P + 63) / 64, KN / 64), 256, 0, s>>>(sm, p_stride, p0, P, KN, out);
+  return hipGetLastError();
+}
 
 hipError_t launch_pack_query_slot(const uint32_t *q_ntt, uint8_t *qatoms, uint32_t col_slot,
                                   uint32_t n_cb, uint32_t R, uint32_t N, uint32_t K,

@@ -101,10 +101,15 @@ struct ScanJob {
   DbDesc db;
   const uint8_t *qatoms;   // query atoms of this job (batched kernel)
   const uint32_t *q_ntt;   // NTT-form query [1][R][2][K][N] (batch-1 kernel)
-  uint32_t *out;           // answer NTT form [B][C][2][K][N]
+  // Answers, NTT form.  Batch-1 kernel: [B][C][2][K][N].  Batched kernel:
+  // slot-major, answer polynomial p = (b C + j) 2 + c of slot s at
+  // out[s * p_stride + p] (s = k N + t), so that a block's stores are whole
+  // contiguous runs; launch_unpack_answers restores [B][C][2][K][N].
+  uint32_t *out;
   uint32_t B;
   uint32_t slot0, n_slots;
   uint32_t cb_stride;      // column blocks per (k, t, ib) in qatoms; 0 = ceil(2B/8)
+  uint32_t p_stride;       // batched kernel: row pitch of out in words; 0 = 2 B C
 };
 
 // A scan kernel variant.  kind 0: batch-1 streaming kernel (jbw row blocks per
@@ -123,5 +128,10 @@ ScanCfg scan_default_mfma(uint32_t B);
 // Scan every job with one variant; jobs are fused into launches of up to 8.
 // kind 0 needs B == 1 for every job, kind 1 any B (query atoms).
 hipError_t launch_scan(const ScanJob *jobs, size_t n, const ScanCfg &cfg, hipStream_t s);
+
+// Polynomials p0 .. p0 + P - 1 of a slot-major answer block sm ([KN][p_stride])
+// into polynomial-major out ([P][KN]); KN must be a multiple of 64.
+hipError_t launch_unpack_answers(const uint32_t *sm, uint32_t p_stride, uint32_t p0, uint32_t P,
+                                 uint32_t KN, uint32_t *out, hipStream_t s);
 
 }  // namespace pir

@@ -80,6 +80,44 @@ __device__ __forceinline__ uint32_t quad_sum_mod(uint32_t s, uint32_t q) {
   return csub(s, q);
 }
 
+// x moved from the lane given by the quad permutation CTRL, 64 bits at a time.
+template <int CTRL>
+__device__ __forceinline__ double quad_perm_f64(double x) {
+  const uint64_t u = __builtin_bit_cast(uint64_t, x);
+  const uint32_t lo = (uint32_t)__builtin_amdgcn_update_dpp(0, (int)(uint32_t)u, CTRL, 0xF, 0xF, false);
+  const uint32_t hi = (uint32_t)__builtin_amdgcn_update_dpp(0, (int)(uint32_t)(u >> 32), CTRL, 0xF, 0xF, false);
+  return __builtin_bit_cast(double, ((uint64_t)hi << 32) | lo);
+}
+
+// One output of the batched scan from its 16 limb sums, in two stages.  This
+// lane holds P[a] = acc[(row, a)][(col, b)] for a = 0..3 and its own b
+// (wb = 2^(7b)); the other three lanes of the quad hold the other b.  The
+// target is  sum_{a,b} P[a][b] * 2^(7(a+b))  mod q.  Everything runs in fp64 on
+// exact integers:
+//  * L = sum_a P[a] 2^(7a) < 2^29 * 2^21.01 < 2^51 (P[a] < 2^29 for R <= 32768);
+//  * r = L - rint(L/q) q is exact (the product and the difference are integers
+//    below 2^53) and |r| <= q/2 + 1;
+//  * z = r * 2^(7b) summed over the quad is below 2^50 in magnitude, and every
+//    lane of the quad ends with the same z (quad_partial);
+//  * y = z - rint(z/q) q is exact with |y| <= q/2 + 1; adding q when y < 0
+//    gives the canonical residue (quad_final).
+// The quotient estimates only choose which multiple of q to subtract, so
+// their rounding never affects the result.
+__device__ __forceinline__ double quad_partial(int p0, int p1, int p2, int p3, double wb,
+                                               double qd, double inv_q) {
+  const double L = (double)p0 + 128.0 * (double)p1 + 16384.0 * (double)p2 + 2097152.0 * (double)p3;
+  const double r = L - __builtin_rint(L * inv_q) * qd;
+  double z = r * wb;
+  z += quad_perm_f64<0xB1>(z);
+  z += quad_perm_f64<0x4E>(z);
+  return z;
+}
+
+__device__ __forceinline__ uint32_t quad_final(double z, double qd, double inv_q, uint32_t q) {
+  const int y = (int)(z - __builtin_rint(z * inv_q) * qd);
+  return (uint32_t)(y < 0 ? y + (int)q : y);
+}
+
 // sum_a P[a] * 2^(7a) mod q for the four limb sums P[a] < 2^31 of one lane.
 // The sum T is exact in 64 bits (< 2^53) and exactly representable as a
 // double, so a double quotient estimate is off by at most one; the int32
@@ -212,16 +250,16 @@ __global__ __launch_bounds__(256) void k_scan_b1(const B1Args args) {
 }
 
 // ---------------------------------------------------------------------------
-constexpr uint32_t kKCB = 4;  // contraction atoms per staged query chunk
+constexpr uint32_t kKCB = 4;  // contraction steps per staged query chunk
 
 struct MfJob {
   DbDesc db;
   const uint8_t *qatoms;  // query atoms [K][N][n_ib][cb_stride]
-  uint32_t *out;          // answer [B][C][2][K][N]
-  uint32_t B, n_cb, cb_stride;
-  uint32_t slot0, n_slots, n_jg, n_cbt;
-  uint32_t ns, n_sg;      // slots per block, slot groups: logical blocks = n_sg * n_jg * n_cbt
-  uint32_t first;
+  uint32_t *out;          // answers, slot-major: [K N][p_stride]
+  uint32_t B, n_cb, cb_stride, p_stride;
+  uint32_t slot0, n_jg, n_cbt;  // work item = (slot, row group, column tile)
+  uint32_t n_items, n_blocks;   // items; blocks (block L takes items L, L + n_blocks, ...)
+  uint32_t first;               // first logical block of this job
 };
 
 struct MfArgs {
@@ -229,81 +267,132 @@ struct MfArgs {
   uint32_t n_jobs, total;
 };
 
-// JBW database row blocks x CBW query column blocks per wave; the four waves of
-// a block take consecutive row blocks of one slot.  The slot takes S steps
-// (n_ib rounded up to the ring depth D; steps past n_ib meet zero query atoms
-// and read valid padding memory); the database-atom ring requests step g + D
-// while step g computes, and query atoms come through double-buffered LDS
-// chunks of kKCB steps.  No load sits under a data-dependent branch, so the
-// load counters stay exact.  (MfJob::ns > 1 is reserved for streaming several
-// slots per block; the launcher sets 1.)
+// Third descriptor word of a raw (unformatted, stride 0) buffer resource.
+constexpr int kBufferWord3 = 0x00020000;
+
+// Instruction-class masks of the scheduling-group builtin.
+constexpr int kSgMfma = 0x008, kSgVmemRead = 0x020, kSgDsRead = 0x100, kSgDsWrite = 0x200;
+
+// Where one work item's operands live, as seen by one wave.
+template <int JBW>
+struct MfItem {
+  uint32_t slot, cb0, ncb;
+  uint32_t jbs[JBW];
+  bool jv[JBW];
+  const uint8_t *rows[JBW];      // first database atom of each row block (wave-uniform)
+  __amdgpu_buffer_rsrc_t qrs;    // the slot's query atoms
+};
+
+template <int JBW, int CBW>
+__device__ __forceinline__ void mf_item(const MfJob &a, uint32_t it, uint32_t wave,
+                                        MfItem<JBW> &m) {
+  const DbDesc &db = a.db;
+  // column tiles of the same rows are adjacent, then row groups of one slot
+  const uint32_t cbt = it % a.n_cbt, rest = it / a.n_cbt;
+  const uint32_t jg = rest % a.n_jg;
+  m.slot = a.slot0 + rest / a.n_jg;
+  m.cb0 = cbt * CBW;
+  m.ncb = min((uint32_t)CBW, a.n_cb - m.cb0);
+#pragma unroll
+  for (int w = 0; w < JBW; ++w) {
+    m.jbs[w] = (jg * 4 + wave) * JBW + w;
+    m.jv[w] = m.jbs[w] < db.n_jb;
+    // rows past C read row block 0: valid memory, results discarded
+    m.rows[w] = db.atoms +
+                ((size_t)m.slot * db.n_jb + (m.jv[w] ? m.jbs[w] : 0)) * db.n_ib * kAtomBytes;
+  }
+  // A raw buffer resource over the slot's query atoms: a load whose offset is
+  // past the resource's size returns zeros, so staging needs no branch.
+  const uint32_t q_bytes = db.n_ib * a.cb_stride * kAtomBytes;
+  m.qrs = __builtin_amdgcn_make_buffer_rsrc((void *)(a.qatoms + (size_t)m.slot * q_bytes), (short)0,
+                                            (int)q_bytes, kBufferWord3);
+}
+
+// A block is four waves; wave w owns row blocks (4 jg + w) JBW .. + JBW - 1 and
+// CBW query column blocks of one work item (slot, jg, column tile).  Blocks
+// are persistent over a strided sequence of items (L, L + n_blocks, ...), so
+// blocks running at the same time work on neighbouring items and share the
+// slot's query atoms in L2.  The contraction of an item runs over S steps
+// (one 32-row atom each, n_ib rounded up to D; steps past n_ib read valid
+// memory and meet zero query atoms).
+//
+// Pipeline, per wave:
+//  * database atoms: a register ring D steps deep; the atom of step s + D is
+//    requested right after the MFMAs of step s have read ring slot s mod D.
+//    Near the end of an item the ring fills with the next item's first steps,
+//    so the epilogue runs while they are in flight;
+//  * query atoms: LDS buffers of kKCB steps, double-buffered.  Chunk n + 1 is
+//    written and published by a barrier one step before chunk n ends (with
+//    one-step B prefetch; at its last step without), and the global loads of
+//    chunk n + 2 (of this item or the next) are issued right after;
+//  * the order inside a step is pinned with scheduling groups, so the
+//    compiler cannot sink the prefetches next to their uses.
+// Every staging condition is wave-uniform, so no load sits under a divergent
+// branch and the memory counters stay exact.
 template <int JBW, int CBW, int D, int OCC>
 __global__ __launch_bounds__(256, OCC) void k_scan_mfma(const MfArgs args) {
-  static_assert(D % kKCB == 0, "ring depth must be a multiple of the query chunk");
-  constexpr uint32_t kBuf = kKCB * CBW * 64;  // uint4 per LDS buffer
-  constexpr uint32_t kPer = (kBuf + 255) / 256;
+  static_assert(D % kKCB == 0 && kKCB >= 2, "ring depth must be a multiple of the query chunk");
+  constexpr uint32_t kAtoms = kKCB * CBW;      // query atoms per chunk
+  constexpr uint32_t kBuf = kAtoms * 64;       // uint4 per LDS buffer
+  constexpr uint32_t kPer = (kAtoms + 3) / 4;  // chunk atoms per wave
+  constexpr int kM = JBW * CBW;                // MFMAs per step
   __shared__ uint4 sq[2 * kBuf];
   const uint32_t Lg = xcd_logical(blockIdx.x, gridDim.x);
   if (Lg >= args.total) return;
   const MfJob &a = args.jobs[find_job(args, Lg)];
   const uint32_t L = Lg - a.first;
   const DbDesc &db = a.db;
-  // column tiles of the same rows are adjacent, then row groups of one slot
-  // group: a database atom's second read and a slot's query atoms hit L2
-  const uint32_t cbt = L % a.n_cbt;
-  const uint32_t rest = L / a.n_cbt;
-  const uint32_t jg = rest % a.n_jg, sg = rest / a.n_jg;
-  const uint32_t s_begin = a.slot0 + sg * a.ns;
-  const uint32_t s_count = min(a.ns, a.slot0 + a.n_slots - s_begin);
   const uint32_t tid = threadIdx.x, lane = tid & 63;
   const uint32_t wave = __builtin_amdgcn_readfirstlane(tid >> 6);
-  const uint32_t n_ib = db.n_ib, n_jb = db.n_jb, n_cb = a.n_cb, cbs = a.cb_stride;
-  const uint32_t cb0 = cbt * CBW;
-  const uint32_t ncb = min((uint32_t)CBW, n_cb - cb0);
-  const uint32_t S = (n_ib + D - 1) / D * D;  // steps per slot
+  const uint32_t n_ib = db.n_ib, cbs = a.cb_stride;
+  // Steps per item: n_ib rounded up to the ring depth, and at least two
+  // chunks, so that the staging lookahead of two chunks never reaches past
+  // the next item.  Extra steps meet zero query atoms; their database reads
+  // stay within the allocation's tail padding (at most 7 atoms past the end).
+  const uint32_t S = (max(n_ib, 2 * kKCB) + D - 1) / D * D;
+  const uint32_t nc = S / kKCB;  // chunks per item
+  const uint32_t lane_off = lane * 16;
 
-  uint32_t jbs[JBW];
-  bool jv[JBW];
-  size_t row_off[JBW];
-#pragma unroll
-  for (int w = 0; w < JBW; ++w) {
-    jbs[w] = (jg * 4 + wave) * JBW + w;
-    jv[w] = jbs[w] < n_jb;
-    // rows past C read row block 0: valid memory, results discarded
-    row_off[w] = (size_t)(jv[w] ? jbs[w] : 0) * n_ib * kAtomBytes;
-  }
-  const size_t slot_stride = (size_t)n_jb * n_ib * kAtomBytes;
-  const uint8_t *atoms_lane = db.atoms + lane * 16;
-  // First atom of ring group (u, ks) for row block w; groups past the block
-  // read the block's first atom (valid memory, never used).  Steps of a slot
-  // past n_ib run into the following atoms or the allocation's tail padding
-  // and meet zero query atoms.
-  auto group_ptr = [&](int w, uint32_t u, uint32_t ks) {
-    const bool ok = u < s_count;
-    const size_t off = (size_t)(s_begin + (ok ? u : 0)) * slot_stride + row_off[w] +
-                       (size_t)(ok ? ks : 0) * kAtomBytes;
-    return atoms_lane + off;
+  uint32_t it = L;
+  MfItem<JBW> cur, nxt;
+  mf_item<JBW, CBW>(a, it, wave, cur);
+  bool has_next = it + a.n_blocks < a.n_items;
+  if (has_next) mf_item<JBW, CBW>(a, it + a.n_blocks, wave, nxt);
+  else nxt = cur;
+
+  // atom of step ks (< S + D) of row block w: this item, else the next item's
+  // step ks - S, else (last item) this item's step 0
+  auto ring_ptr = [&](int w, uint32_t ks) {
+    const uint8_t *p = ks < S ? cur.rows[w] + (size_t)ks * kAtomBytes
+                              : has_next ? nxt.rows[w] + (size_t)(ks - S) * kAtomBytes : cur.rows[w];
+    return reinterpret_cast<const v4i *>(p + lane_off);
   };
-  const uint4 *qbase = reinterpret_cast<const uint4 *>(a.qatoms);
-  // query atoms of the chunk starting at step ks of slot u (zero past the block)
-  auto stage_load = [&](uint32_t u, uint32_t ks, uint4 (&st)[kPer]) {
-    const bool uok = u < s_count;
-    const uint4 *qs = qbase + (size_t)(s_begin + (uok ? u : 0)) * n_ib * cbs * 64;
+  // query atoms of chunk n (< nc + 2) counted from this item's first: atom
+  // (kk, c) of a chunk goes to wave (kk CBW + c) mod 4; zero past n_ib, past
+  // the batch's column blocks and past the last item
+  auto stage_load = [&](uint32_t n, v4i (&st)[kPer]) {
+    const bool mine = n < nc;
+    const uint32_t ln = mine ? n : n - nc;
+    const bool live = mine || has_next;
+    const uint32_t cb0 = mine ? cur.cb0 : nxt.cb0, ncb = mine ? cur.ncb : nxt.ncb;
+    const __amdgpu_buffer_rsrc_t rs = mine ? cur.qrs : nxt.qrs;
 #pragma unroll
     for (uint32_t r = 0; r < kPer; ++r) {
-      const uint32_t idx = tid + 256 * r;
-      const uint32_t kk = idx / (CBW * 64), c = (idx / 64) % CBW, l = idx & 63;
-      const bool ok = uok && idx < kBuf && ks + kk < n_ib && c < ncb;
-      const uint4 v = qs[ok ? ((size_t)(ks + kk) * cbs + cb0 + c) * 64 + l : 0];
-      st[r] = ok ? v : make_uint4(0, 0, 0, 0);
+      const uint32_t ai = wave + 4 * r;
+      const uint32_t kk = ai / CBW, c = ai % CBW, ks = ln * kKCB + kk;
+      const bool ok = live && (kAtoms % 4 == 0 || ai < kAtoms) && ks < n_ib && c < ncb;
+      const uint32_t off = ok ? ((ks * cbs + cb0 + c) * 64 + lane) * 16 : 0x80000000u;
+      st[r] = __builtin_bit_cast(v4i, __builtin_amdgcn_raw_buffer_load_b128(rs, off, 0, 0));
     }
   };
-  auto stage_store = [&](uint4 *buf, const uint4 (&st)[kPer]) {
+  auto stage_store = [&](uint4 *buf, const v4i (&st)[kPer]) {
 #pragma unroll
-    for (uint32_t r = 0; r < kPer; ++r)
-      if (tid + 256 * r < kBuf) buf[tid + 256 * r] = st[r];
+    for (uint32_t r = 0; r < kPer; ++r) {
+      const uint32_t ai = wave + 4 * r;
+      if (kAtoms % 4 == 0 || ai < kAtoms)
+        buf[ai * 64 + lane] = make_uint4(st[r].x, st[r].y, st[r].z, st[r].w);
+    }
   };
-  v4i bcur[CBW], bnext[CBW];
   auto b_read = [&](const uint4 *src, v4i (&bv)[CBW]) {
 #pragma unroll
     for (int c = 0; c < CBW; ++c) {
@@ -312,103 +401,127 @@ __global__ __launch_bounds__(256, OCC) void k_scan_mfma(const MfArgs args) {
     }
   };
 
-  v16i acc[JBW][CBW];
-#pragma unroll
-  for (int w = 0; w < JBW; ++w)
-#pragma unroll
-    for (int c = 0; c < CBW; ++c) acc[w][c] = v16i{};
-
   v4i ring[D][JBW];
 #pragma unroll
-  for (int w = 0; w < JBW; ++w) {
-    const uint8_t *p = group_ptr(w, 0, 0);
+  for (int d = 0; d < D; ++d)
 #pragma unroll
-    for (int d = 0; d < D; ++d)
-      ring[d][w] = __builtin_nontemporal_load(reinterpret_cast<const v4i *>(p + d * kAtomBytes));
-  }
-  uint4 st[kPer];
-  stage_load(0, 0, st);
+    for (int w = 0; w < JBW; ++w) ring[d][w] = __builtin_nontemporal_load(ring_ptr(w, d));
+  v4i st[kPer];
+  stage_load(0, st);
   stage_store(sq, st);
+  stage_load(1, st);
   __syncthreads();
-  b_read(sq, bcur);
+  // One wave per SIMD: the B operands of step s + 1 are read during step s.
+  // Two waves per SIMD: each step reads its own B operands first and the other
+  // wave's MFMAs cover the LDS latency (saving the registers of a second set).
+  constexpr bool kPf = OCC == 1;
+  // Step of a chunk that publishes the next chunk.  The buffer it overwrites
+  // was last read for the previous chunk's final step; that read comes before
+  // the previous chunk's publishing barrier only if it is a prefetch (issued
+  // one step early), so without prefetch the publish waits for the final step.
+  constexpr int kPub = kPf ? (int)kKCB - 2 : (int)kKCB - 1;
+  v4i bcur[CBW], bnext[CBW];
+  if (kPf) b_read(sq, bcur);
 
-  // epilogue constants.  32x32 result: lane holds column lane & 31 (= 4 cc + b)
-  // and, in register r, row 8*(r>>2) + 4*(lane>>5) + (r&3)  (row = 4 jl + a).
-  const uint32_t b = lane & 3, cc = (lane >> 2) & 7, hi = lane >> 5;
-  const size_t KN = (size_t)db.K * db.N;
   const uint32_t ncol = 2 * a.B;
-  uint32_t chunk = 0;  // chunks completed (LDS buffer parity)
-
-  {
-    const uint32_t u = 0;
-    for (uint32_t ks0 = 0; ks0 < S; ks0 += D) {
-      // the group that refills the ring: next D steps of this slot or the next slot
-      const bool same = ks0 + D < S;
-      const uint32_t ur = same ? u : u + 1, kr = same ? ks0 + D : 0;
-      const uint8_t *rp[JBW];
+  uint32_t chunk = 0;  // chunks completed by this block (LDS buffer parity)
+  for (;;) {
+    v16i acc[JBW][CBW];
 #pragma unroll
-      for (int w = 0; w < JBW; ++w) rp[w] = group_ptr(w, ur, kr);
+    for (int w = 0; w < JBW; ++w)
+#pragma unroll
+      for (int c = 0; c < CBW; ++c) acc[w][c] = v16i{};
+    uint32_t cl = 0;  // chunk within the item
+    for (uint32_t ks0 = 0; ks0 < S; ks0 += D) {
 #pragma unroll
       for (int d = 0; d < D; ++d) {
-        const int kk = d % kKCB;
-        if (kk == 0) {
-          // next chunk, in flight during this one
-          if (d + kKCB < D) stage_load(u, ks0 + d + kKCB, st);
-          else stage_load(ur, kr, st);
+        const int kk = d % (int)kKCB;
+        const uint4 *bcur_buf = sq + (chunk & 1) * kBuf;
+        const uint4 *bnxt_buf = sq + ((chunk + 1) & 1) * kBuf;
+        if (kPf) {
+          // B operands of the next step: this chunk, or the next one
+          // (published by the barrier of the previous step)
+          if (kk + 1 < (int)kKCB) b_read(bcur_buf + (kk + 1) * CBW * 64, bnext);
+          else b_read(bnxt_buf, bnext);
+        } else {
+          b_read(bcur_buf + kk * CBW * 64, bcur);
         }
-        if (kk + 1 < (int)kKCB) b_read(sq + (chunk & 1) * kBuf + (kk + 1) * CBW * 64, bnext);
-#pragma unroll
-        for (int c = 0; c < CBW; ++c)
-#pragma unroll
-          for (int w = 0; w < JBW; ++w)
-            acc[w][c] = __builtin_amdgcn_mfma_i32_32x32x32_i8(ring[d][w], bcur[c], acc[w][c], 0, 0, 0);
 #pragma unroll
         for (int w = 0; w < JBW; ++w)
-          ring[d][w] = __builtin_nontemporal_load(reinterpret_cast<const v4i *>(rp[w] + d * kAtomBytes));
-        if (kk == (int)kKCB - 1) {
-          ++chunk;
-          stage_store(sq + (chunk & 1) * kBuf, st);
+#pragma unroll
+          for (int c = 0; c < CBW; ++c)
+            acc[w][c] =
+                __builtin_amdgcn_mfma_i32_32x32x32_i8(ring[d][w], bcur[c], acc[w][c], 0, 0, 0);
+#pragma unroll
+        for (int w = 0; w < JBW; ++w)
+          ring[d][w] = __builtin_nontemporal_load(ring_ptr(w, ks0 + D + d));
+        if (kPf) {
+#pragma unroll
+          for (int i = 0; i < kM; ++i) {
+            __builtin_amdgcn_sched_group_barrier(kSgMfma, 1, 0);
+            if (i < CBW) __builtin_amdgcn_sched_group_barrier(kSgDsRead, 1, 0);
+          }
+        } else {
+          __builtin_amdgcn_sched_group_barrier(kSgDsRead, CBW, 0);
+          __builtin_amdgcn_sched_group_barrier(kSgMfma, kM, 0);
+        }
+        __builtin_amdgcn_sched_group_barrier(kSgVmemRead, JBW, 0);
+        if (kk == kPub) {
+          // publish chunk + 1 (after this step's ring loads), then fetch
+          // chunk + 2 into the staging registers
+          __builtin_amdgcn_sched_group_barrier(kSgDsWrite, kPer, 0);
+          stage_store(sq + ((chunk + 1) & 1) * kBuf, st);
           __syncthreads();
-          b_read(sq + (chunk & 1) * kBuf, bnext);
+          stage_load(cl + 2, st);
         }
+        if (kk == (int)kKCB - 1) ++chunk, ++cl;
+        if (kPf) {
 #pragma unroll
-        for (int c = 0; c < CBW; ++c) bcur[c] = bnext[c];
-      }
-    }
-  }
-  {
-    // the slot is complete: reduce and store
-    const uint32_t slot = s_begin;
-    const uint32_t k = slot >> db.log2n, t = slot & (db.N - 1);
-    const DevPrime &P = db.primes[k];
-    const uint32_t q = P.q;
-    uint32_t wv[4], wsh[4];
-#pragma unroll
-    for (int r = 0; r < 4; ++r) {
-      wv[r] = P.w[r + b];
-      wsh[r] = P.w_sh[r + b];
-    }
-#pragma unroll
-    for (int w = 0; w < JBW; ++w) {
-#pragma unroll
-      for (int c = 0; c < CBW; ++c) {
-        const uint32_t col = (cb0 + c) * 8 + cc;
-#pragma unroll
-        for (int qq = 0; qq < 4; ++qq) {
-          // sum over limbs a in the lane (Shoup products), then over b across lanes
-          uint32_t s2 = 0;
-#pragma unroll
-          for (int r = 0; r < 4; ++r)
-            s2 += mul_shoup((uint32_t)acc[w][c][4 * qq + r], wv[r], wsh[r], q);
-          s2 = csub(s2, 4 * q);
-          s2 = csub(s2, 2 * q);
-          const uint32_t sv = quad_sum_mod(s2, q);
-          const uint32_t j = jbs[w] * 8 + 2 * qq + hi;
-          if (jv[w] && (uint32_t)c < ncb && b == 0 && j < db.C && col < ncol)
-            a.out[(((size_t)(col >> 1) * db.C + j) * 2 + (col & 1)) * KN + (size_t)k * db.N + t] = sv;
+          for (int c = 0; c < CBW; ++c) bcur[c] = bnext[c];
         }
       }
     }
+    // Epilogue of the item.  32x32 result: lane holds column lane & 31
+    // (= 4 cc + b) and, in register r, row 8 (r >> 2) + 4 (lane >> 5) + (r & 3)
+    // (row = 4 jl + a), so the four registers 4 qq .. 4 qq + 3 of a lane are
+    // the limbs a = 0..3 of one (row, column, b) and the four lanes b = 0..3 of
+    // a quad complete the output.
+    {
+      const uint32_t b = lane & 3, cc = (lane >> 2) & 7, hi = lane >> 5;
+      const uint32_t q = db.primes[cur.slot >> db.log2n].q;
+      const double qd = (double)q, inv_q = 1.0 / qd, wb = (double)(1u << (7 * b));
+      // After quad_partial the four lanes of a quad agree; lane b finishes and
+      // stores the output of register group qq = b, i.e. row 8 jb + 2 b + hi.
+      // Answer polynomial p = (query C + j) 2 + component with query = col / 2
+      // and component = col % 2: in one store the 16 lanes of a query write 16
+      // consecutive words (8 rows x 2 components) of the slot's row.
+      const uint32_t jrow = 2 * b + hi;
+      uint32_t *out_lane = a.out + (size_t)cur.slot * a.p_stride +
+                           ((size_t)(cur.cb0 * 4 + (cc >> 1)) * db.C + jrow) * 2 + (cc & 1);
+#pragma unroll
+      for (int w = 0; w < JBW; ++w) {
+#pragma unroll
+        for (int c = 0; c < CBW; ++c) {
+          double z[4];
+#pragma unroll
+          for (int qq = 0; qq < 4; ++qq)
+            z[qq] = quad_partial(acc[w][c][4 * qq], acc[w][c][4 * qq + 1], acc[w][c][4 * qq + 2],
+                                 acc[w][c][4 * qq + 3], wb, qd, inv_q);
+          const double zb = b == 0 ? z[0] : b == 1 ? z[1] : b == 2 ? z[2] : z[3];
+          const uint32_t mine = quad_final(zb, qd, inv_q, q);
+          const uint32_t col = (cur.cb0 + c) * 8 + cc, j = cur.jbs[w] * 8 + jrow;
+          if (cur.jv[w] && (uint32_t)c < cur.ncb && j < db.C && col < ncol)
+            out_lane[((size_t)c * 4 * db.C + (size_t)cur.jbs[w] * 8) * 2] = mine;
+        }
+      }
+    }
+    if (!has_next) break;
+    // the ring, the published chunk and the staging registers already hold
+    // the next item's first steps
+    it += a.n_blocks;
+    cur = nxt;
+    has_next = it + a.n_blocks < a.n_items;
+    if (has_next) mf_item<JBW, CBW>(a, it + a.n_blocks, wave, nxt);
   }
 }
 
@@ -437,6 +550,11 @@ hipError_t run_b1(const ScanJob *jobs, size_t n, hipStream_t s) {
   return hipGetLastError();
 }
 
+// Blocks of a persistent batched launch: each takes about kItemsPerBlock work
+// items, and a launch has at least kMinBlocks per wave-slot of occupancy
+// (four per CU on 256 CUs) when it has that many items.
+constexpr uint32_t kItemsPerBlock = 16, kMinBlocks = 1024;
+
 template <int JBW, int CBW, int D, int OCC>
 hipError_t run_mfma(const ScanJob *jobs, size_t n, hipStream_t s) {
   MfArgs a{};
@@ -450,19 +568,17 @@ hipError_t run_mfma(const ScanJob *jobs, size_t n, hipStream_t s) {
     m.B = job.B;
     m.n_cb = (2 * job.B + kCB - 1) / kCB;
     m.cb_stride = job.cb_stride ? job.cb_stride : m.n_cb;
-    m.slot0 = job.slot0;
-    m.n_slots = job.n_slots;
+    m.p_stride = job.p_stride ? job.p_stride : 2 * job.B * job.db.C;
     m.n_jg = (job.db.n_jb + 4 * JBW - 1) / (4 * JBW);
     m.n_cbt = (m.n_cb + CBW - 1) / CBW;
-    // enough blocks to fill the chip several times over, each streaming up to
-    // 16 slots so that only the first pays the pipeline fill
-    const uint32_t per_slot = m.n_jg * m.n_cbt;
-    (void)per_slot;
-    const uint32_t ns = 1;  // one slot per block
-    m.ns = ns;
-    m.n_sg = (m.n_slots + ns - 1) / ns;
+    m.slot0 = job.slot0;
+    m.n_items = job.n_slots * m.n_jg * m.n_cbt;
+    // persistent blocks: about kItemsPerBlock items each, but never fewer
+    // blocks than the chip holds at once
+    m.n_blocks = std::max(std::min(m.n_items, kMinBlocks * OCC),
+                          (m.n_items + kItemsPerBlock - 1) / kItemsPerBlock);
     m.first = total;
-    total += m.n_cbt * m.n_sg * m.n_jg;
+    total += m.n_blocks;
   }
   a.n_jobs = (uint32_t)n;
   a.total = total;
@@ -490,8 +606,8 @@ const Variant kVariants[] = {
     // batched MFMA
     MF(1, 1, 8, 1), MF(2, 1, 8, 1), MF(4, 1, 8, 1), MF(4, 1, 8, 2),
     MF(1, 2, 8, 1), MF(2, 2, 8, 1), MF(4, 2, 8, 1), MF(2, 2, 8, 2),
-    MF(1, 4, 8, 1), MF(2, 4, 8, 1), MF(2, 4, 4, 2), MF(4, 4, 8, 1), MF(4, 4, 4, 1),
-    MF(1, 8, 8, 1), MF(2, 8, 8, 1), MF(2, 8, 4, 1), MF(1, 8, 4, 2),
+    MF(1, 4, 8, 1), MF(2, 4, 8, 1), MF(2, 4, 4, 2), MF(2, 4, 8, 2), MF(4, 4, 8, 1), MF(4, 4, 4, 1),
+    MF(1, 8, 8, 1), MF(2, 8, 8, 1), MF(2, 8, 4, 1), MF(1, 8, 4, 2), MF(1, 8, 8, 2),
 };
 #undef MF
 
@@ -534,6 +650,7 @@ hipError_t launch_scan(const ScanJob *jobs, size_t n, const ScanCfg &cfg, hipStr
     if (cfg.kind == 0 ? (j.B != 1 || !j.q_ntt) : !j.qatoms) return hipErrorInvalidValue;
     if (j.n_slots == 0 || j.slot0 + j.n_slots > j.db.K * j.db.N) return hipErrorInvalidValue;
     if (j.cb_stride && j.cb_stride * kCB < 2 * j.B) return hipErrorInvalidValue;
+    if (cfg.kind == 1 && j.p_stride && j.p_stride < 2 * j.B * j.db.C) return hipErrorInvalidValue;
   }
   for (const Variant &v : kVariants) {
     if (v.cfg.kind != cfg.kind || v.cfg.jbw != cfg.jbw || v.cfg.unr != cfg.unr || v.cfg.nt != cfg.nt)

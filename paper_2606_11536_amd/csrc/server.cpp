@@ -27,7 +27,8 @@ struct pir_server {
   uint32_t max_batch = 0, n_cb = 0, n_chunks = 0, n_slots = 0, chunk_len = 0;
   uint32_t chunk = 0;
   uint8_t *qatoms = nullptr;
-  uint32_t *ans = nullptr, *scratch = nullptr;
+  uint32_t *ans = nullptr;      // answer state, slot-major: [K N][2 max_batch C]
+  uint32_t *scratch = nullptr;  // NTT-form query of an admission
   size_t qatoms_bytes = 0, ans_bytes = 0, scratch_bytes = 0;
   struct Slot {
     bool active = false;
@@ -168,15 +169,16 @@ pir_status pir_server_step(pir_server *s, pir_stream stream, uint32_t *admitted,
   if (b_eff) {
     const uint32_t slot0 = s->chunk * s->chunk_len;
     const uint32_t n = std::min(s->chunk_len, s->n_slots - slot0);
-    ScanJob job{d, s->qatoms, nullptr, s->ans, b_eff, slot0, n, s->n_cb};
+    ScanJob job{d, s->qatoms, nullptr, s->ans, b_eff, slot0, n, s->n_cb, 2 * s->max_batch * d.C};
     HIP_OR_FAIL(ctx, launch_scan(&job, 1, server_scan_cfg(ctx, d, b_eff), st));
     // 3. queries that have now met every range finish
     for (uint32_t k = 0; k < s->max_batch; ++k) {
       pir_server::Slot &sl = s->slots[k];
       if (!sl.active || ++sl.done < s->n_chunks) continue;
-      uint32_t *a = s->ans + (size_t)k * (answer_bytes(d) / 4);
-      HIP_OR_FAIL(ctx, launch_ntt(a, (size_t)d.C * 2 * d.K, d.K, d.log2n, d.primes, true, st));
-      HIP_OR_FAIL(ctx, hipMemcpyAsync(sl.out, a, answer_bytes(d), hipMemcpyDeviceToDevice, st));
+      // the slot's polynomials out of the slot-major state, then the INTT in place
+      HIP_OR_FAIL(ctx, launch_unpack_answers(s->ans, 2 * s->max_batch * d.C, 2 * k * d.C, 2 * d.C,
+                                             d.K * d.N, sl.out, st));
+      HIP_OR_FAIL(ctx, launch_ntt(sl.out, (size_t)d.C * 2 * d.K, d.K, d.log2n, d.primes, true, st));
       hipEvent_t ev;
       HIP_OR_FAIL(ctx, hipEventCreateWithFlags(&ev, hipEventDisableTiming));
       HIP_OR_FAIL(ctx, hipEventRecord(ev, st));

@@ -81,7 +81,7 @@ SIGNATURES = {
                                     ct.POINTER(ct.c_uint64)]),
 }
 
-STAGES = {"ntt": 0, "pack": 1, "scan": 2, "intt": 3}
+STAGES = {"ntt": 0, "pack": 1, "scan": 2, "intt": 3, "unpack": 4}
 
 
 class PirError(RuntimeError):
