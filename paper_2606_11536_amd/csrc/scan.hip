@@ -381,7 +381,9 @@ __global__ __launch_bounds__(256, OCC) void k_scan_mfma(const MfArgs args) {
       const uint32_t ai = wave + 4 * r;
       const uint32_t kk = ai / CBW, c = ai % CBW, ks = ln * kKCB + kk;
       const bool ok = live && (kAtoms % 4 == 0 || ai < kAtoms) && ks < n_ib && c < ncb;
-      const uint32_t off = ok ? ((ks * cbs + cb0 + c) * 64 + lane) * 16 : 0x80000000u;
+      // offsets are below 2^26; setting bit 31 puts a dead load past the
+      // resource's end (zeros) without a branch
+      const uint32_t off = (((ks * cbs + cb0 + c) * 64 + lane) * 16) | ((uint32_t)!ok << 31);
       st[r] = __builtin_bit_cast(v4i, __builtin_amdgcn_raw_buffer_load_b128(rs, off, 0, 0));
     }
   };
@@ -473,6 +475,8 @@ __global__ __launch_bounds__(256, OCC) void k_scan_mfma(const MfArgs args) {
           stage_store(sq + ((chunk + 1) & 1) * kBuf, st);
           __syncthreads();
           stage_load(cl + 2, st);
+          // keep the staging loads here, a chunk ahead of their use
+          __builtin_amdgcn_sched_barrier(0);
         }
         if (kk == (int)kKCB - 1) ++chunk, ++cl;
         if (kPf) {
