@@ -641,7 +641,7 @@ ScanCfg scan_default_mfma(uint32_t B) {
 }
 
 ScanCfg scan_default(uint32_t B) {
-  if (B == 1) return ScanCfg{0, 2, 8, 1};
+  if (B == 1) return ScanCfg{0, 4, 8, 1};
   const uint32_t cbw = cbw_for(B);
   const uint8_t lg = cbw == 8 ? 3 : cbw == 4 ? 2 : cbw == 2 ? 1 : 0;
   return ScanCfg{1, 2, 8, lg};
