@@ -770,7 +770,7 @@ pir_status pir_tune_batch(pir_ctx *ctx, const pir_job *jobs, size_t n_jobs, pir_
   if ((st = ensure_ws(ctx, p.bytes())) != PIR_OK) return st;
   hipStream_t s = (hipStream_t)stream;
   place_batch(jobs, n_jobs, (uint8_t *)ctx->ws, p);
-  HIP_OR_FAIL(ctx, hipMemsetAsync(ctx->ws, 0, p.bytes(), s));
+  HIP_OR_FAIL(ctx, launch_fill_tuning((uint32_t *)ctx->ws, p.bytes() / 4, s));
   hipEvent_t e0, e1;
   HIP_OR_FAIL(ctx, hipEventCreate(&e0));
   HIP_OR_FAIL(ctx, hipEventCreate(&e1));
@@ -839,8 +839,9 @@ pir_status pir_tune(pir_ctx *ctx, const pir_db *db, uint32_t B, pir_stream strea
   if (st != PIR_OK) return st;
   hipStream_t s = (hipStream_t)stream;
   uint8_t *base = (uint8_t *)ctx->ws;
-  // Timing does not depend on values; start from a defined state all the same.
-  HIP_OR_FAIL(ctx, hipMemsetAsync(base, 0, qb + ab + ob, s));
+  // Time on random-looking operands: the matrix cores draw more power (and
+  // clock lower) on them than on zeros, which can change the ranking.
+  HIP_OR_FAIL(ctx, launch_fill_tuning((uint32_t *)base, (qb + ab + ob) / 4, s));
   ScanJob job{d, base + qb, (const uint32_t *)base, (uint32_t *)(base + qb + ab), B, 0, d.K * d.N, 0,
               0};
   const std::vector<ScanCfg> cands = scan_candidates(B);

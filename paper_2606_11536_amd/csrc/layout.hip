@@ -6,6 +6,8 @@
 // residues in LDS -- read as 128-byte runs along t -- and writes 32 whole
 // 1 KiB atoms, one per slot t, so both sides of the transposition move full
 // contiguous lines.
+#include <algorithm>
+
 #include "device_util.h"
 #include "pir_internal.h"
 
@@ -189,7 +191,30 @@ __global__ __launch_bounds__(256) void k_unpack_answers(const uint32_t *__restri
   }
 }
 
+// Timing data for the autotuner: word i = hash(i) & 0x0F7F7F7F (every byte a
+// valid 7-bit limb, every word below 2^28).  Timing depends on the data: the
+// matrix cores draw more power on random operands than on zeros.
+__global__ void k_fill_tuning(uint32_t *__restrict__ p, size_t n) {
+  for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < n;
+       i += (size_t)gridDim.x * blockDim.x) {
+    uint32_t x = (uint32_t)i * 0x9E3779B1u ^ (uint32_t)(i >> 32);
+    x ^= x >> 16;
+    x *= 0x85EBCA6Bu;
+    x ^= x >> 13;
+    x *= 0xC2B2AE35u;
+    x ^= x >> 16;
+    p[i] = x & 0x0F7F7F7Fu;
+  }
+}
+
 }  // namespace
+
+hipError_t launch_fill_tuning(uint32_t *p, size_t n_words, hipStream_t s) {
+  if (n_words == 0) return hipSuccess;
+  const size_t blocks = std::min<size_t>((n_words + 255) / 256, 65536);
+  k_fill_tuning<<<(unsigned)blocks, 256, 0, s>>>(p, n_words);
+  return hipGetLastError();
+}
 
 hipError_t launch_unpack_answers(const uint32_t *sm, uint32_t p_stride, uint32_t p0, uint32_t P,
                                  uint32_t KN, uint32_t *out, hipStream_t s) {

@@ -129,6 +129,9 @@ ScanCfg scan_default_mfma(uint32_t B);
 // kind 0 needs B == 1 for every job, kind 1 any B (query atoms).
 hipError_t launch_scan(const ScanJob *jobs, size_t n, const ScanCfg &cfg, hipStream_t s);
 
+// Pseudo-random words (bytes < 128, words < 2^28) for autotuner timing runs.
+hipError_t launch_fill_tuning(uint32_t *p, size_t n_words, hipStream_t s);
+
 // Polynomials p0 .. p0 + P - 1 of a slot-major answer block sm ([KN][p_stride])
 // into polynomial-major out ([P][KN]); KN must be a multiple of 64.
 hipError_t launch_unpack_answers(const uint32_t *sm, uint32_t p_stride, uint32_t p0, uint32_t P,
