@@ -99,19 +99,27 @@ __global__ __launch_bounds__(256) void k_pack_query(const uint32_t *__restrict__
   const uint32_t k = blockIdx.z / n_cb, cb = blockIdx.z % n_cb;
   const uint32_t tt = tid & 31, p = tid >> 5;
   const uint32_t ncol = 2 * B;
-#pragma unroll 4
+  // All 32 loads of a thread are issued before the first is used (the tile's
+  // 32 KiB in flight at once); rows past R and columns past 2B read element 0
+  // and are masked to zero, so no load sits under a branch.
+  uint32_t v[32];
+#pragma unroll
   for (uint32_t r = 0; r < 32; ++r) {
     const uint32_t pi = p + 8 * r;
     const uint32_t il = pi >> 3, cc = pi & 7;
     const uint32_t i = ib * 32 + il, col = cb * 8 + cc;
-    uint32_t v = 0;
-    if (i < R && col < ncol)
-      v = q[((((size_t)(col >> 1) * R + i) * 2 + (col & 1)) * K + k) * N + t0 + tt];
-    lds[(il * 8 + cc) * kPad + tt] = v;
+    const bool ok = i < R && col < ncol;
+    const size_t at = ((((size_t)(col >> 1) * R + i) * 2 + (col & 1)) * K + k) * N + t0 + tt;
+    v[r] = q[ok ? at : 0] & (ok ? ~0u : 0u);
+  }
+#pragma unroll
+  for (uint32_t r = 0; r < 32; ++r) {
+    const uint32_t pi = p + 8 * r;
+    lds[((pi >> 3) * 8 + (pi & 7)) * kPad + tt] = v[r];
   }
   __syncthreads();
   uint4 *out = reinterpret_cast<uint4 *>(qatoms);
-#pragma unroll 2
+#pragma unroll
   for (uint32_t r = 0; r < 8; ++r) {
     const uint32_t w = tid + 256 * r;
     const uint32_t tl = w >> 6, lane = w & 63;
@@ -178,16 +186,21 @@ __global__ __launch_bounds__(256) void k_unpack_answers(const uint32_t *__restri
   __shared__ uint32_t tile[64][65];
   const uint32_t pb = blockIdx.x * 64, s0 = blockIdx.y * 64;
   const uint32_t tx = threadIdx.x & 63, ty = threadIdx.x >> 6;
-#pragma unroll 4
-  for (uint32_t r = ty; r < 64; r += 4) {
-    const uint32_t p = pb + tx;
-    tile[r][tx] = p < P ? sm[(size_t)(s0 + r) * p_stride + p0 + p] : 0u;
-  }
+  // all 16 loads in flight before the first LDS store; polynomials past P
+  // read a valid word and are masked
+  const uint32_t p = pb + tx;
+  const bool ok = p < P;
+  uint32_t v[16];
+#pragma unroll
+  for (uint32_t r = 0; r < 16; ++r)
+    v[r] = sm[(size_t)(s0 + ty + 4 * r) * p_stride + p0 + (ok ? p : 0)] & (ok ? ~0u : 0u);
+#pragma unroll
+  for (uint32_t r = 0; r < 16; ++r) tile[ty + 4 * r][tx] = v[r];
   __syncthreads();
-#pragma unroll 4
-  for (uint32_t r = ty; r < 64; r += 4) {
-    const uint32_t p = pb + r;
-    if (p < P) out[(size_t)p * KN + s0 + tx] = tile[tx][r];
+#pragma unroll
+  for (uint32_t r = 0; r < 16; ++r) {
+    const uint32_t pr = pb + ty + 4 * r;
+    if (pr < P) out[(size_t)pr * KN + s0 + tx] = tile[tx][ty + 4 * r];
   }
 }
 
