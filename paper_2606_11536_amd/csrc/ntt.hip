@@ -12,9 +12,16 @@
 // Inverse: Gentleman-Sande stages with half-sizes 1, 2, ..., N/2 and the
 // inverse twiddles, then the factor N^-1.
 //
-// Arithmetic: Shoup multiplication by precomputed twiddle quotients; forward
-// values stay lazily in [0, 4q) and inverse values in [0, 2q) (both < 2^30),
-// reduced to [0, q) once at the end.
+// Arithmetic: exact integers held in fp64 (full-rate FMA, where 32-bit
+// integer multiplies run at quarter rate).  The product y*w mod q is
+//   p = y*w (rounded), e = fma(y, w, -p)  (so y*w = p + e exactly),
+//   r = fma(-rint(p/q), q, p) + e,
+// exact because p - rint(p/q) q is an integer of magnitude below q/2 + q/1024
+// and e is at most half an ulp of p; |r| < 0.51 q.  Values are not reduced
+// between stages: forward stages add at most 0.51 q per stage (|x| < 8q),
+// inverse stages at most double (|x| < 2^12 q < 2^41), so every product
+// stays below 2^70 and every sum is an exact integer below 2^53.  Each value
+// is reduced to [0, q) once at the end.
 #include "device_util.h"
 #include "pir_internal.h"
 
@@ -41,6 +48,19 @@ struct Geo {
   }
 };
 
+// y * w mod q as an exact integer of magnitude below 0.51 q (see above).
+__device__ __forceinline__ double mulmod_f64(double y, double w, double q, double inv_q) {
+  const double p = y * w;
+  const double e = __builtin_fma(y, w, -p);
+  return __builtin_fma(-__builtin_rint(p * inv_q), q, p) + e;
+}
+
+// An exact integer v (|v| < 2^53) reduced to [0, q).
+__device__ __forceinline__ uint32_t reduce_f64(double v, double q, double inv_q) {
+  const double r = __builtin_fma(-__builtin_rint(v * inv_q), q, v);  // |r| < 0.51 q
+  return (uint32_t)(int)(r < 0.0 ? r + q : r);
+}
+
 // Index of register e in round r for thread tid.
 template <int LOGN, bool INV, int R>
 __device__ __forceinline__ uint32_t ridx(uint32_t tid, int e) {
@@ -55,13 +75,12 @@ __device__ __forceinline__ uint32_t ridx(uint32_t tid, int e) {
 }
 
 template <int LOGN, bool INV, int R>
-__device__ __forceinline__ void round_compute(uint32_t (&x)[Geo<LOGN>::E], uint32_t tid,
-                                              const uint32_t *__restrict__ tw,
-                                              const uint32_t *__restrict__ twsh, uint32_t q) {
+__device__ __forceinline__ void round_compute(double (&x)[Geo<LOGN>::E], uint32_t tid,
+                                              const uint32_t *__restrict__ tw, double q,
+                                              double inv_q) {
   using G = Geo<LOGN>;
   constexpr int S = G::s(R, INV);
   constexpr int LL = G::logL(R, INV);
-  const uint32_t q2 = 2 * q;
 #pragma unroll
   for (int step = 0; step < S; ++step) {
     const int u = INV ? step : (S - 1 - step);
@@ -72,27 +91,25 @@ __device__ __forceinline__ void round_compute(uint32_t (&x)[Geo<LOGN>::E], uint3
       const int f = e + (1 << u);
       const uint32_t idx = ridx<LOGN, INV, R>(tid, e);
       const uint32_t ti = (uint32_t)(G::N + idx) >> (logh + 1);
-      const uint32_t w = tw[ti], wsh = twsh[ti];
-      const uint32_t X = x[e], Y = x[f];
+      const double w = (double)tw[ti];
+      const double X = x[e], Y = x[f];
       if (!INV) {
-        const uint32_t Xr = csub(X, q2);
-        const uint32_t T = mul_shoup(Y, w, wsh, q);
-        x[e] = Xr + T;
-        x[f] = Xr - T + q2;
+        const double T = mulmod_f64(Y, w, q, inv_q);
+        x[e] = X + T;
+        x[f] = X - T;
       } else {
-        x[e] = csub(X + Y, q2);
-        x[f] = mul_shoup(X - Y + q2, w, wsh, q);
+        x[e] = X + Y;
+        x[f] = mulmod_f64(X - Y, w, q, inv_q);
       }
     }
   }
 }
 
 template <int LOGN, bool INV, int R>
-__device__ __forceinline__ void rounds_from(uint32_t (&x)[Geo<LOGN>::E], uint32_t tid,
-                                            uint32_t *sm, const uint32_t *tw,
-                                            const uint32_t *twsh, uint32_t q) {
+__device__ __forceinline__ void rounds_from(double (&x)[Geo<LOGN>::E], uint32_t tid, double *sm,
+                                            const uint32_t *tw, double q, double inv_q) {
   using G = Geo<LOGN>;
-  round_compute<LOGN, INV, R>(x, tid, tw, twsh, q);
+  round_compute<LOGN, INV, R>(x, tid, tw, q, inv_q);
   if constexpr (R + 1 < G::ROUNDS) {
     if (R > 0) __syncthreads();  // the previous round's reads are done
 #pragma unroll
@@ -100,31 +117,24 @@ __device__ __forceinline__ void rounds_from(uint32_t (&x)[Geo<LOGN>::E], uint32_
     __syncthreads();
 #pragma unroll
     for (int e = 0; e < G::E; ++e) x[e] = sm[ridx<LOGN, INV, R + 1>(tid, e)];
-    rounds_from<LOGN, INV, R + 1>(x, tid, sm, tw, twsh, q);
+    rounds_from<LOGN, INV, R + 1>(x, tid, sm, tw, q, inv_q);
   }
 }
 
-// Transform the values in x (loaded with round-0 indexing); on return x holds
-// canonical residues in [0, q) laid out with last-round indexing.
+// Transform x (exact integers, loaded with round-0 indexing); on return out
+// holds canonical residues in [0, q) laid out with last-round indexing.
 template <int LOGN, bool INV>
-__device__ __forceinline__ void transform(uint32_t (&x)[Geo<LOGN>::E], uint32_t tid,
-                                          uint32_t *sm, const DevPrime &P) {
+__device__ __forceinline__ void transform(double (&x)[Geo<LOGN>::E],
+                                          uint32_t (&out)[Geo<LOGN>::E], uint32_t tid,
+                                          double *sm, const DevPrime &P) {
   constexpr int N = Geo<LOGN>::N;
-  const uint32_t q = P.q;
+  const double q = (double)P.q, inv_q = 1.0 / q;
   const uint32_t *tw = P.tw + (INV ? 2 * N : 0);
-  const uint32_t *twsh = P.tw + (INV ? 3 * N : N);
-  rounds_from<LOGN, INV, 0>(x, tid, sm, tw, twsh, q);
+  rounds_from<LOGN, INV, 0>(x, tid, sm, tw, q, inv_q);
+  const double ninv = (double)P.ninv;
 #pragma unroll
-  for (int e = 0; e < Geo<LOGN>::E; ++e) {
-    uint32_t v = x[e];
-    if (!INV) {
-      v = csub(v, 2 * q);
-      v = csub(v, q);
-    } else {
-      v = csub(mul_shoup(v, P.ninv, P.ninv_sh, q), q);
-    }
-    x[e] = v;
-  }
+  for (int e = 0; e < Geo<LOGN>::E; ++e)
+    out[e] = reduce_f64(INV ? mulmod_f64(x[e], ninv, q, inv_q) : x[e], q, inv_q);
 }
 
 template <int LOGN, bool INV>
@@ -132,19 +142,20 @@ __global__ __launch_bounds__(kThreads) void k_ntt_rows(const uint32_t *__restric
                                                        uint32_t *__restrict__ dst, uint32_t K,
                                                        const DevPrime *__restrict__ primes) {
   using G = Geo<LOGN>;
-  __shared__ uint32_t sm[G::N];
+  __shared__ double sm[G::N];
   const uint32_t tid = threadIdx.x;
   const size_t row = blockIdx.x;
   const DevPrime &P = primes[row % K];
   const uint32_t *in = src + row * G::N;
   uint32_t *out = dst + row * G::N;
-  uint32_t x[G::E];
+  double x[G::E];
 #pragma unroll
-  for (int e = 0; e < G::E; ++e) x[e] = in[ridx<LOGN, INV, 0>(tid, e)];
-  transform<LOGN, INV>(x, tid, sm, P);
+  for (int e = 0; e < G::E; ++e) x[e] = (double)in[ridx<LOGN, INV, 0>(tid, e)];
+  uint32_t y[G::E];
+  transform<LOGN, INV>(x, y, tid, sm, P);
   constexpr int LAST = G::ROUNDS - 1;
 #pragma unroll
-  for (int e = 0; e < G::E; ++e) out[ridx<LOGN, INV, LAST>(tid, e)] = x[e];
+  for (int e = 0; e < G::E; ++e) out[ridx<LOGN, INV, LAST>(tid, e)] = y[e];
 }
 
 // raw: [rows][N] uint8 (rows = S*C of the slab); out: [K][rows][N].
@@ -154,25 +165,26 @@ __global__ __launch_bounds__(kThreads) void k_lift_ntt(const uint8_t *__restrict
                                                        uint32_t valid_rows,
                                                        const DevPrime *__restrict__ primes) {
   using G = Geo<LOGN>;
-  __shared__ uint32_t sm[G::N];
+  __shared__ double sm[G::N];
   const uint32_t tid = threadIdx.x;
   const uint32_t row = blockIdx.x;
   const uint32_t k = blockIdx.y;
   const DevPrime &P = primes[k];
-  uint32_t x[G::E];
+  double x[G::E];
   if (row < valid_rows) {
     const uint8_t *in = raw + (size_t)row * G::N;
 #pragma unroll
-    for (int e = 0; e < G::E; ++e) x[e] = in[ridx<LOGN, false, 0>(tid, e)];
+    for (int e = 0; e < G::E; ++e) x[e] = (double)in[ridx<LOGN, false, 0>(tid, e)];
   } else {
 #pragma unroll
-    for (int e = 0; e < G::E; ++e) x[e] = 0;
+    for (int e = 0; e < G::E; ++e) x[e] = 0.0;
   }
-  transform<LOGN, false>(x, tid, sm, P);
+  uint32_t y[G::E];
+  transform<LOGN, false>(x, y, tid, sm, P);
   uint32_t *o = out + ((size_t)k * rows + row) * G::N;
   constexpr int LAST = G::ROUNDS - 1;
 #pragma unroll
-  for (int e = 0; e < G::E; ++e) o[ridx<LOGN, false, LAST>(tid, e)] = x[e];
+  for (int e = 0; e < G::E; ++e) o[ridx<LOGN, false, LAST>(tid, e)] = y[e];
 }
 
 template <bool INV>
