@@ -422,6 +422,7 @@ __global__ __launch_bounds__(256, OCC) void k_scan_mfma(const MfArgs args) {
   // the previous chunk's publishing barrier only if it is a prefetch (issued
   // one step early), so without prefetch the publish waits for the final step.
   constexpr int kPub = kPf ? (int)kKCB - 2 : (int)kKCB - 1;
+  constexpr int kPre = kM < 2 ? kM : 2;  // MFMAs issued ahead of a publishing barrier
   v4i bcur[CBW], bnext[CBW];
   if (kPf) b_read(sq, bcur);
 
@@ -440,35 +441,61 @@ __global__ __launch_bounds__(256, OCC) void k_scan_mfma(const MfArgs args) {
         const int kk = d % (int)kKCB;
         const uint4 *bcur_buf = sq + (chunk & 1) * kBuf;
         const uint4 *bnxt_buf = sq + ((chunk + 1) & 1) * kBuf;
-        if (kPf) {
-          // B operands of the next step: this chunk, or the next one
-          // (published by the barrier of the previous step)
-          if (kk + 1 < (int)kKCB) b_read(bcur_buf + (kk + 1) * CBW * 64, bnext);
-          else b_read(bnxt_buf, bnext);
-        } else {
-          b_read(bcur_buf + kk * CBW * 64, bcur);
-        }
+        // MFMAs of tiles [i0, i1) of this step (tile i = row block i / CBW,
+        // column block i % CBW)
+        auto mfmas = [&](int i0, int i1) {
 #pragma unroll
-        for (int w = 0; w < JBW; ++w)
+          for (int i = i0; i < i1; ++i)
+            acc[i / CBW][i % CBW] = __builtin_amdgcn_mfma_i32_32x32x32_i8(
+                ring[d][i / CBW], bcur[i % CBW], acc[i / CBW][i % CBW], 0, 0, 0);
+        };
+        if (kPf && kk == (int)kKCB - 1) {
+          // The chunk published last step becomes visible at a barrier taken
+          // behind this step's first kPre MFMAs (they keep the matrix pipe busy
+          // while the waves meet); then the next chunk's staging loads, then the
+          // B operands of the next step from the new chunk.
+          mfmas(0, kPre);
+          // pin them ahead of the barrier (the MFMA builtin touches no memory,
+          // so nothing else keeps the compiler from sinking it past)
 #pragma unroll
-          for (int c = 0; c < CBW; ++c)
-            acc[w][c] =
-                __builtin_amdgcn_mfma_i32_32x32x32_i8(ring[d][w], bcur[c], acc[w][c], 0, 0, 0);
+          for (int i = 0; i < kPre; ++i) asm volatile("" : "+a"(acc[i / CBW][i % CBW]));
+          __syncthreads();
+          stage_load(cl + 2, st);
+          __builtin_amdgcn_sched_barrier(0);
+          b_read(bnxt_buf, bnext);
+          mfmas(kPre, kM);
 #pragma unroll
-        for (int w = 0; w < JBW; ++w)
-          ring[d][w] = __builtin_nontemporal_load(ring_ptr(w, ks0 + D + d));
-        if (kPf) {
+          for (int i = kPre; i < kM; ++i) {
+            __builtin_amdgcn_sched_group_barrier(kSgMfma, 1, 0);
+            if (i - kPre < CBW) __builtin_amdgcn_sched_group_barrier(kSgDsRead, 1, 0);
+          }
+        } else if (kPf) {
+          // B operands of the next step (this chunk)
+          b_read(bcur_buf + (kk + 1) * CBW * 64, bnext);
+          mfmas(0, kM);
+          if (kk == kPub) {
+            // publish chunk + 1: the staging stores ride between this step's
+            // MFMAs, after its next-step B reads
+            stage_store(sq + ((chunk + 1) & 1) * kBuf, st);
+          }
 #pragma unroll
           for (int i = 0; i < kM; ++i) {
             __builtin_amdgcn_sched_group_barrier(kSgMfma, 1, 0);
             if (i < CBW) __builtin_amdgcn_sched_group_barrier(kSgDsRead, 1, 0);
+            else if (kk == kPub && i - CBW < (int)kPer)
+              __builtin_amdgcn_sched_group_barrier(kSgDsWrite, 1, 0);
           }
         } else {
+          b_read(bcur_buf + kk * CBW * 64, bcur);
+          mfmas(0, kM);
           __builtin_amdgcn_sched_group_barrier(kSgDsRead, CBW, 0);
           __builtin_amdgcn_sched_group_barrier(kSgMfma, kM, 0);
         }
+#pragma unroll
+        for (int w = 0; w < JBW; ++w)
+          ring[d][w] = __builtin_nontemporal_load(ring_ptr(w, ks0 + D + d));
         __builtin_amdgcn_sched_group_barrier(kSgVmemRead, JBW, 0);
-        if (kk == kPub) {
+        if (!kPf && kk == kPub) {
           // publish chunk + 1 (after this step's ring loads), then fetch
           // chunk + 2 into the staging registers
           __builtin_amdgcn_sched_group_barrier(kSgDsWrite, kPer, 0);
