@@ -413,16 +413,19 @@ __global__ __launch_bounds__(256, OCC) void k_scan_mfma(const MfArgs args) {
   stage_store(sq, st);
   stage_load(1, st);
   __syncthreads();
-  // One wave per SIMD: the B operands of step s + 1 are read during step s.
-  // Two waves per SIMD: each step reads its own B operands first and the other
-  // wave's MFMAs cover the LDS latency (saving the registers of a second set).
-  constexpr bool kPf = OCC == 1;
+  // Normally the B operands of step s + 1 are read during step s.  Two waves
+  // per SIMD with a deep ring have no registers for a second set: each step
+  // then reads its own B operands first and the other wave's MFMAs cover the
+  // LDS latency.
+  constexpr bool kPf = OCC == 1 || JBW * D * 4 + CBW * 8 <= 64;
   // Step of a chunk that publishes the next chunk.  The buffer it overwrites
   // was last read for the previous chunk's final step; that read comes before
   // the previous chunk's publishing barrier only if it is a prefetch (issued
   // one step early), so without prefetch the publish waits for the final step.
   constexpr int kPub = kPf ? (int)kKCB - 2 : (int)kKCB - 1;
-  constexpr int kPre = kM < 2 ? kM : 2;  // MFMAs issued ahead of a publishing barrier
+  // MFMAs issued ahead of a publishing barrier (one wave per SIMD only: their
+  // pin keeps the accumulators in AGPRs, which two waves per SIMD cannot afford)
+  constexpr int kPre = OCC > 1 ? 0 : kM < 2 ? kM : 2;
   v4i bcur[CBW], bnext[CBW];
   if (kPf) b_read(sq, bcur);
 
