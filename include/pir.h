@@ -121,9 +121,10 @@ pir_status pir_ctx_reserve(pir_ctx *ctx, size_t bytes);
  * stores the result in the library's scan layout (slot-major, limb-planar
  * tiles; opaque).  `raw` is device memory if raw_is_device != 0, else host
  * memory (copied in slabs through pinned staging).  1 <= R <= PIR_MAX_R,
- * 1 <= C <= PIR_MAX_C.  The database holds R_pad*C_pad*N*K*4 bytes of device
- * memory (R_pad = R rounded up to 32, C_pad = C rounded up to 8); BUDGET if
- * that exceeds the context's budget.  The call returns after `raw` has been
+ * 1 <= C <= PIR_MAX_C.  The database holds R_pad*C_pad*N*K*4 + 65536 bytes
+ * of device memory (R_pad = R rounded up to 64, C_pad = C rounded up to 8; the
+ * last 64 KiB are padding that the batched scan may read but never uses);
+ * BUDGET if that exceeds the context's budget.  The call returns after `raw` has been
  * consumed (it synchronizes `stream`), so the caller may free `raw` at once.
  * *out receives the database; release it with pir_db_free. */
 pir_status pir_db_load_ntt(pir_ctx *ctx, const pir_params *params, const uint8_t *raw,
