@@ -447,7 +447,7 @@ def main() -> int:
     scan_avg_ms = scan_ms / max(scan_n, 1)
     alg = scan_alg_bytes(log2n, K, R, C, B)
     achieved = alg / (scan_avg_ms * 1e-3) / 1e9
-    kernel = "k_scan_b1" if B == 1 else "k_scan_mfma"
+    kernel = ctx.scan_kernel(db, B)
     out = {
         "metric": METRIC,
         "value": round(value, 3),

@@ -206,6 +206,12 @@ uint32_t pir_scan_variants(uint32_t B);
  * at batch size B. */
 pir_status pir_scan_select(pir_ctx *ctx, const pir_db *db, uint32_t B, uint32_t index);
 
+/* Name of the kernel ("k_scan_b1", "k_scan_b1r" or "k_scan_mfma") that a
+ * single-job scan of `db` at batch size B launches with the context's current
+ * choice (for profiles and reports).  The string is static; NULL for a NULL
+ * context or database or B outside [1, PIR_MAX_BATCH]. */
+const char *pir_scan_kernel(const pir_ctx *ctx, const pir_db *db, uint32_t B);
+
 /* Autotune: time every variant for `db` at batch size B on `stream` (on
  * workspace contents; values do not affect timing), keep the fastest, and wait
  * for the stream.  If `report` is not NULL it receives up to report_len bytes

@@ -815,6 +815,11 @@ uint32_t pir_scan_variants(uint32_t B) {
   return (B >= 1 && B <= PIR_MAX_BATCH) ? (uint32_t)scan_candidates(B).size() : 0;
 }
 
+const char *pir_scan_kernel(const pir_ctx *ctx, const pir_db *db, uint32_t B) {
+  if (!ctx || !db || B < 1 || B > PIR_MAX_BATCH) return nullptr;
+  return scan_kernel_name(chosen_cfg(ctx, db->desc, B), db->desc);
+}
+
 pir_status pir_scan_select(pir_ctx *ctx, const pir_db *db, uint32_t B, uint32_t index) {
   if (!ctx) return PIR_ERR_INVALID_ARG;
   if (!db || B < 1 || B > PIR_MAX_BATCH) return fail(ctx, PIR_ERR_INVALID_ARG, "bad db or B");

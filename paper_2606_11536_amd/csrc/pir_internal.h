@@ -125,6 +125,8 @@ std::vector<ScanCfg> scan_candidates(uint32_t B);
 ScanCfg scan_default(uint32_t B);
 // Default batched-kernel (kind 1) variant for B columns pairs, including B = 1.
 ScanCfg scan_default_mfma(uint32_t B);
+// Name of the kernel that variant cfg launches for database d.
+const char *scan_kernel_name(const ScanCfg &cfg, const DbDesc &d);
 // Scan every job with one variant; jobs are fused into launches of up to 8.
 // kind 0 needs B == 1 for every job, kind 1 any B (query atoms).
 hipError_t launch_scan(const ScanJob *jobs, size_t n, const ScanCfg &cfg, hipStream_t s);

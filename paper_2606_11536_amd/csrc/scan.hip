@@ -40,6 +40,9 @@ typedef int v16i __attribute__((ext_vector_type(16)));
 
 constexpr uint32_t kB1Chunk = 64;  // query ibs split into LDS per chunk (16 KiB)
 
+// Instruction-class masks of the scheduling-group builtin.
+constexpr int kSgMfma = 0x008, kSgVmemRead = 0x020, kSgDsRead = 0x100, kSgDsWrite = 0x200;
+
 // Scan launches take a table of up to kMaxFused jobs; the logical block
 // index space is the concatenation of the jobs' spaces (job j owns logical
 // blocks [first, first + blocks)).  A block finds its job by a uniform
@@ -143,6 +146,49 @@ __device__ __forceinline__ v4i load_atom16(const uint8_t *p) {
   }
 }
 
+// Split the slot's query residues of atoms ib0 .. ib0 + nib - 1 into limb bytes
+// in LDS: item (ibl, half, c, e4) covers i = 32 (ib0+ibl) + 16 half + 4 e4 + u,
+// u < 4, and writes one word per limb b at LDS lane (half, 4c + b), bytes
+// 4 e4 .. 4 e4 + 3.  Rows past R read as zero.
+__device__ __forceinline__ void b1_split_query(uint32_t *sq, const uint32_t *qbase, size_t qrow,
+                                               uint32_t R, uint32_t ib0, uint32_t nib,
+                                               uint32_t tid) {
+  for (uint32_t idx = tid; idx < nib * 16; idx += 256) {
+    const uint32_t ibl = idx >> 4, r = idx & 15;
+    const uint32_t half = r >> 3, c = (r >> 2) & 1, e4 = r & 3;
+    const uint32_t i0 = (ib0 + ibl) * 32 + half * 16 + e4 * 4;
+    uint32_t v[4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) v[u] = (i0 + u < R) ? qbase[((size_t)(i0 + u) * 2 + c) * qrow] : 0u;
+#pragma unroll
+    for (uint32_t b = 0; b < 4; ++b) {
+      uint32_t w = 0;
+#pragma unroll
+      for (int u = 0; u < 4; ++u) w |= ((v[u] >> (7 * b)) & 127u) << (8 * u);
+      sq[((ibl * 2 + half) * 8 + c * 4 + b) * 4 + e4] = w;
+    }
+  }
+}
+
+// Epilogue of both batch-1 kernels for row block jb.  Lane holds rows
+// 4*(lane>>4) + r (row = 4 jl' + a, a = r) of column lane & 15 (= 4 cc + b).
+__device__ __forceinline__ void b1_epilogue(const v4i (&acc)[2], uint32_t jb, uint32_t lane,
+                                            const DbDesc &db, const DevPrime &P, uint32_t k,
+                                            uint32_t t, uint32_t *out) {
+  const uint32_t b = lane & 3, cc = (lane >> 2) & 3, jlp = lane >> 4;
+  const uint32_t q = P.q, wb = P.w[b], wbsh = P.w_sh[b];
+  const double inv_q = 1.0 / (double)q;
+  const size_t KN = (size_t)db.K * db.N;
+#pragma unroll
+  for (int jh = 0; jh < 2; ++jh) {
+    const v4i &A = acc[jh];
+    const uint32_t u = limb_sum_mod(A[0], A[1], A[2], A[3], q, inv_q);
+    const uint32_t s = quad_sum_mod(mul_shoup(u, wb, wbsh, q), q);
+    const uint32_t j = jb * 8 + jh * 4 + jlp;
+    if (b == 0 && cc < 2 && j < db.C) out[((size_t)j * 2 + cc) * KN + (size_t)k * db.N + t] = s;
+  }
+}
+
 template <int JBW, int UNR, bool NT>
 __global__ __launch_bounds__(256) void k_scan_b1(const B1Args args) {
   __shared__ uint32_t sq[kB1Chunk * 64];
@@ -154,7 +200,6 @@ __global__ __launch_bounds__(256) void k_scan_b1(const B1Args args) {
   const uint32_t slot = a.slot0 + L % a.n_slots, jchunk = L / a.n_slots;
   const uint32_t k = slot >> db.log2n, t = slot & (db.N - 1);
   const DevPrime &P = db.primes[k];
-  const uint32_t q = P.q;
 
   const uint32_t tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
   const uint32_t g = lane >> 4, m = lane & 15;
@@ -175,25 +220,7 @@ __global__ __launch_bounds__(256) void k_scan_b1(const B1Args args) {
   for (uint32_t ib0 = 0; ib0 < n_ib; ib0 += kB1Chunk) {
     const uint32_t nib = min(kB1Chunk, n_ib - ib0);  // even: R_pad is a multiple of 64
     __syncthreads();
-    // Split the slot's query residues into limb bytes: item (ibl, half, c, e4)
-    // covers i = 32 (ib0+ibl) + 16 half + 4 e4 + u, u < 4, and writes one word
-    // per limb b at LDS lane (half, 4c + b), bytes 4 e4 .. 4 e4 + 3.
-    for (uint32_t idx = tid; idx < nib * 16; idx += 256) {
-      const uint32_t ibl = idx >> 4, r = idx & 15;
-      const uint32_t half = r >> 3, c = (r >> 2) & 1, e4 = r & 3;
-      const uint32_t i0 = (ib0 + ibl) * 32 + half * 16 + e4 * 4;
-      uint32_t v[4];
-#pragma unroll
-      for (int u = 0; u < 4; ++u)
-        v[u] = (i0 + u < db.R) ? qbase[((size_t)(i0 + u) * 2 + c) * qrow] : 0u;
-#pragma unroll
-      for (uint32_t b = 0; b < 4; ++b) {
-        uint32_t w = 0;
-#pragma unroll
-        for (int u = 0; u < 4; ++u) w |= ((v[u] >> (7 * b)) & 127u) << (8 * u);
-        sq[((ibl * 2 + half) * 8 + c * 4 + b) * 4 + e4] = w;
-      }
-    }
+    b1_split_query(sq, qbase, qrow, db.R, ib0, nib, tid);
     __syncthreads();
     const uint32_t nkb = nib >> 1;
 #pragma unroll
@@ -228,25 +255,125 @@ __global__ __launch_bounds__(256) void k_scan_b1(const B1Args args) {
     }
   }
 
-  // Epilogue.  Lane holds rows 4*(lane>>4) + r (row = 4 jl' + a, a = r) of
-  // column lane & 15 (= 4 cc + b).
-  const uint32_t b = lane & 3, cc = (lane >> 2) & 3, jlp = lane >> 4;
-  const uint32_t wb = P.w[b], wbsh = P.w_sh[b];
-  const double inv_q = 1.0 / (double)q;
-  const size_t KN = (size_t)db.K * db.N;
 #pragma unroll
   for (int w = 0; w < JBW; ++w) {
     const uint32_t jb = jb_begin + wave + 4 * w;
     if (jb >= jb_end) break;
+    b1_epilogue(acc[w], jb, lane, db, P, k, t, a.out);
+  }
+}
+
+// Batch-1 scan with a continuous load stream.  Each wave walks its row blocks
+// w = 0 .. nw-1 and, within each, the k-blocks of the current query chunk as
+// one sequence through a register ring D k-blocks deep: the MFMAs of k-block
+// s are followed by the loads of k-block s + D.  In the last D k-blocks of a
+// row those loads come from the next row block, or from the next chunk's first
+// row block, so the loads in flight never drain between rows; the first row's
+// ring is requested before the query split.  Scheduling groups keep the
+// order LDS read, two MFMAs, two loads per k-block.  Needs every chunk's
+// k-block count to be a multiple of D (the launcher checks).
+template <int JBW, int D, bool NT>
+__global__ __launch_bounds__(256) void k_scan_b1r(const B1Args args) {
+  __shared__ uint32_t sq[kB1Chunk * 64];
+  const uint32_t Lg = xcd_logical(blockIdx.x, gridDim.x);
+  if (Lg >= args.total) return;
+  const B1Job &a = args.jobs[find_job(args, Lg)];
+  const uint32_t L = Lg - a.first;
+  const DbDesc &db = a.db;
+  const uint32_t slot = a.slot0 + L % a.n_slots, jchunk = L / a.n_slots;
+  const uint32_t k = slot >> db.log2n, t = slot & (db.N - 1);
+  const DevPrime &P = db.primes[k];
+  const uint32_t q = P.q;
+
+  const uint32_t tid = threadIdx.x, wave = __builtin_amdgcn_readfirstlane(tid >> 6), lane = tid & 63;
+  const uint32_t g = lane >> 4, m = lane & 15;
+  const uint32_t n_ib = db.n_ib, n_jb = db.n_jb;
+  const uint32_t jb_begin = jchunk * a.jpb;
+  const uint32_t jb_end = min(jb_begin + a.jpb, n_jb);
+  // row blocks of this wave: jb_begin + wave + 4 w for w < nw
+  const uint32_t nw = jb_begin + wave < jb_end ? min((uint32_t)JBW, (jb_end - jb_begin - wave + 3) / 4) : 0;
+  const uint8_t *slot_atoms = db.atoms + (size_t)slot * n_jb * n_ib * kAtomBytes;
+  const uint32_t lane_off = (g >> 1) * 1024 + (g & 1) * 512 + m * 16;
+  const bool bzero = m >= 8;
+  const size_t qrow = (size_t)db.K * db.N;
+  const uint32_t *qbase = a.q + (size_t)k * db.N + t;
+  const uint4 *sq4 = reinterpret_cast<const uint4 *>(sq);
+  auto row_ptr = [&](uint32_t w, uint32_t ib0) {
+    return slot_atoms + ((size_t)(jb_begin + wave + 4 * w) * n_ib + ib0) * kAtomBytes + lane_off;
+  };
+
+  v4i acc[JBW][2];
 #pragma unroll
-    for (int jh = 0; jh < 2; ++jh) {
-      const v4i &A = acc[w][jh];
-      const uint32_t u = limb_sum_mod(A[0], A[1], A[2], A[3], q, inv_q);
-      const uint32_t s = quad_sum_mod(mul_shoup(u, wb, wbsh, q), q);
-      const uint32_t j = jb * 8 + jh * 4 + jlp;
-      if (b == 0 && cc < 2 && j < db.C) a.out[((size_t)j * 2 + cc) * KN + (size_t)k * db.N + t] = s;
+  for (int w = 0; w < JBW; ++w) acc[w][0] = acc[w][1] = v4i{0, 0, 0, 0};
+  v4i r0[D], r1[D];
+  if (nw > 0) {
+    const uint8_t *p = row_ptr(0, 0);
+#pragma unroll
+    for (int d = 0; d < D; ++d) {
+      r0[d] = load_atom16<NT>(p + (size_t)d * 2048);
+      r1[d] = load_atom16<NT>(p + (size_t)d * 2048 + 256);
     }
   }
+
+  for (uint32_t ib0 = 0; ib0 < n_ib; ib0 += kB1Chunk) {
+    const uint32_t nib = min(kB1Chunk, n_ib - ib0);
+    const uint32_t nkb = nib >> 1, ib_next = ib0 + kB1Chunk;
+    __syncthreads();
+    b1_split_query(sq, qbase, qrow, db.R, ib0, nib, tid);
+    __syncthreads();
+#pragma unroll
+    for (int w = 0; w < JBW; ++w) {
+      if ((uint32_t)w < nw) {
+      auto mma = [&](const v4i &x0, const v4i &x1, uint32_t kb) {
+        const uint4 x = sq4[(2 * kb + (g >> 1)) * 16 + (g & 1) * 8 + (m & 7)];
+        const v4i bv = bzero ? v4i{0, 0, 0, 0} : v4i{(int)x.x, (int)x.y, (int)x.z, (int)x.w};
+        acc[w][0] = __builtin_amdgcn_mfma_i32_16x16x64_i8(x0, bv, acc[w][0], 0, 0, 0);
+        acc[w][1] = __builtin_amdgcn_mfma_i32_16x16x64_i8(x1, bv, acc[w][1], 0, 0, 0);
+      };
+      const uint8_t *base = row_ptr(w, ib0);
+      uint32_t kb0 = 0;
+      for (; kb0 + D < nkb; kb0 += D) {
+#pragma unroll
+        for (int d = 0; d < D; ++d) {
+          mma(r0[d], r1[d], kb0 + d);
+          r0[d] = load_atom16<NT>(base + (size_t)(kb0 + D + d) * 2048);
+          r1[d] = load_atom16<NT>(base + (size_t)(kb0 + D + d) * 2048 + 256);
+        }
+#pragma unroll
+        for (int d = 0; d < D; ++d) {
+          __builtin_amdgcn_sched_group_barrier(kSgDsRead, 1, 0);
+          __builtin_amdgcn_sched_group_barrier(kSgMfma, 2, 0);
+          __builtin_amdgcn_sched_group_barrier(kSgVmemRead, 2, 0);
+        }
+      }
+      // last D k-blocks of the row: refill from the next row, else from the
+      // next chunk's first row, else not at all
+      const bool more_row = (uint32_t)w + 1 < nw;
+      if (more_row || ib_next < n_ib) {
+        const uint8_t *nb = more_row ? row_ptr(w + 1, ib0) : row_ptr(0, ib_next);
+#pragma unroll
+        for (int d = 0; d < D; ++d) {
+          mma(r0[d], r1[d], kb0 + d);
+          r0[d] = load_atom16<NT>(nb + (size_t)d * 2048);
+          r1[d] = load_atom16<NT>(nb + (size_t)d * 2048 + 256);
+        }
+#pragma unroll
+        for (int d = 0; d < D; ++d) {
+          __builtin_amdgcn_sched_group_barrier(kSgDsRead, 1, 0);
+          __builtin_amdgcn_sched_group_barrier(kSgMfma, 2, 0);
+          __builtin_amdgcn_sched_group_barrier(kSgVmemRead, 2, 0);
+        }
+      } else {
+#pragma unroll
+        for (int d = 0; d < D; ++d) mma(r0[d], r1[d], kb0 + d);
+      }
+      }
+    }
+  }
+
+#pragma unroll
+  for (int w = 0; w < JBW; ++w)
+    if ((uint32_t)w < nw) b1_epilogue(acc[w], jb_begin + wave + 4 * w, lane, db, P, k, t, a.out);
 }
 
 // ---------------------------------------------------------------------------
@@ -270,8 +397,6 @@ struct MfArgs {
 // Third descriptor word of a raw (unformatted, stride 0) buffer resource.
 constexpr int kBufferWord3 = 0x00020000;
 
-// Instruction-class masks of the scheduling-group builtin.
-constexpr int kSgMfma = 0x008, kSgVmemRead = 0x020, kSgDsRead = 0x100, kSgDsWrite = 0x200;
 
 // Where one work item's operands live, as seen by one wave.
 template <int JBW>
@@ -584,6 +709,35 @@ hipError_t run_b1(const ScanJob *jobs, size_t n, hipStream_t s) {
   return hipGetLastError();
 }
 
+// The ring kernel when every query chunk's k-block count (kB1Chunk / 2, and
+// half the last chunk's atoms) is a multiple of D; else the grouped kernel.
+template <int JBW, int D, bool NT>
+hipError_t run_b1r(const ScanJob *jobs, size_t n, hipStream_t s) {
+  for (size_t i = 0; i < n; ++i) {
+    const uint32_t tail = jobs[i].db.n_ib % kB1Chunk;
+    if ((kB1Chunk / 2) % D != 0 || (tail / 2) % D != 0) return run_b1<JBW, D, NT>(jobs, n, s);
+  }
+  B1Args a{};
+  uint32_t total = 0;
+  for (size_t i = 0; i < n; ++i) {
+    const ScanJob &job = jobs[i];
+    B1Job &b = a.jobs[i];
+    b.db = job.db;
+    b.q = job.q_ntt;
+    b.out = job.out;
+    b.slot0 = job.slot0;
+    b.n_slots = job.n_slots;
+    b.jpb = 4 * JBW;
+    b.first = total;
+    total += b.n_slots * ((job.db.n_jb + b.jpb - 1) / b.jpb);
+  }
+  a.n_jobs = (uint32_t)n;
+  a.total = total;
+  if (total == 0) return hipSuccess;
+  k_scan_b1r<JBW, D, NT><<<round8(total), 256, 0, s>>>(a);
+  return hipGetLastError();
+}
+
 // Blocks of a persistent batched launch: each takes about kItemsPerBlock work
 // items, and a launch has at least kMinBlocks per wave-slot of occupancy
 // (four per CU on 256 CUs) when it has that many items.
@@ -628,15 +782,16 @@ struct Variant {
   ScanFn fn;
 };
 
+// ScanCfg for kind 0: jbw, unr = k-blocks in flight, nt = nontemporal | ring << 1.
 // ScanCfg for kind 1: jbw, unr = ring depth D, nt = log2(CBW) | (OCC - 1) << 4.
 #define MF(J, C, D, O) \
   {{1, J, D, (C == 8 ? 3 : C == 4 ? 2 : C == 2 ? 1 : 0) | ((O - 1) << 4)}, run_mfma<J, C, D, O>}
 const Variant kVariants[] = {
-    // batch-1 streaming: (kind 0, jbw, unroll, nontemporal)
-    {{0, 8, 4, 0}, run_b1<8, 4, false>}, {{0, 8, 8, 0}, run_b1<8, 8, false>},
-    {{0, 4, 4, 0}, run_b1<4, 4, false>}, {{0, 4, 8, 0}, run_b1<4, 8, false>},
-    {{0, 2, 8, 0}, run_b1<2, 8, false>}, {{0, 8, 4, 1}, run_b1<8, 4, true>},
-    {{0, 4, 8, 1}, run_b1<4, 8, true>},  {{0, 2, 8, 1}, run_b1<2, 8, true>},
+    // batch-1 streaming, grouped loads and ring
+    {{0, 8, 4, 1}, run_b1<8, 4, true>},  {{0, 4, 8, 1}, run_b1<4, 8, true>},
+    {{0, 2, 8, 1}, run_b1<2, 8, true>},  {{0, 4, 4, 3}, run_b1r<4, 4, true>},
+    {{0, 2, 8, 3}, run_b1r<2, 8, true>}, {{0, 4, 8, 3}, run_b1r<4, 8, true>},
+    {{0, 2, 4, 3}, run_b1r<2, 4, true>}, {{0, 4, 2, 3}, run_b1r<4, 2, true>},
     // batched MFMA
     MF(1, 1, 8, 1), MF(2, 1, 8, 1), MF(4, 1, 8, 1), MF(4, 1, 8, 2),
     MF(1, 2, 8, 1), MF(2, 2, 8, 1), MF(4, 2, 8, 1), MF(2, 2, 8, 2),
@@ -671,10 +826,17 @@ ScanCfg scan_default_mfma(uint32_t B) {
 }
 
 ScanCfg scan_default(uint32_t B) {
-  if (B == 1) return ScanCfg{0, 4, 8, 1};
+  if (B == 1) return ScanCfg{0, 4, 4, 3};
   const uint32_t cbw = cbw_for(B);
   const uint8_t lg = cbw == 8 ? 3 : cbw == 4 ? 2 : cbw == 2 ? 1 : 0;
   return ScanCfg{1, 2, 8, lg};
+}
+
+const char *scan_kernel_name(const ScanCfg &cfg, const DbDesc &d) {
+  if (cfg.kind == 1) return "k_scan_mfma";
+  const uint32_t tail = d.n_ib % kB1Chunk;
+  const bool ring = (cfg.nt & 2) && (kB1Chunk / 2) % cfg.unr == 0 && (tail / 2) % cfg.unr == 0;
+  return ring ? "k_scan_b1r" : "k_scan_b1";
 }
 
 hipError_t launch_scan(const ScanJob *jobs, size_t n, const ScanCfg &cfg, hipStream_t s) {

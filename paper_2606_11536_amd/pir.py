@@ -63,6 +63,7 @@ SIGNATURES = {
     "pir_answer_batch": (ct.c_int, [_P, ct.POINTER(CJob), ct.c_size_t, _P]),
     "pir_scan_variants": (ct.c_uint32, [_U32]),
     "pir_scan_select": (ct.c_int, [_P, _P, _U32, _U32]),
+    "pir_scan_kernel": (ct.c_char_p, [_P, _P, _U32]),
     "pir_tune": (ct.c_int, [_P, _P, _U32, _P, ct.c_char_p, ct.c_size_t]),
     "pir_tune_batch": (ct.c_int, [_P, ct.POINTER(CJob), ct.c_size_t, _P, ct.c_char_p,
                                   ct.c_size_t]),
@@ -309,6 +310,13 @@ class Context:
     def scan_select(self, db: Database, B: int, index: int) -> None:
         """Use scan variant `index` for databases shaped like `db` at batch size B."""
         _check(lib.pir_scan_select(self.handle, db.handle, B, index), self.handle)
+
+    def scan_kernel(self, db: Database, B: int) -> str:
+        """Name of the kernel a scan of (db, B) launches with the current choice."""
+        name = lib.pir_scan_kernel(self.handle, db.handle, B)
+        if name is None:
+            raise PirError(f"pir_scan_kernel: bad arguments (B={B})")
+        return name.decode()
 
     def tune(self, db: Database, B: int, stream=None) -> str:
         """Time every scan variant for (db, B), keep the fastest; returns the report."""

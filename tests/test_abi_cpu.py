@@ -71,6 +71,10 @@ def test_params_validation_codes():
     assert pir.lib.pir_find_primes(11, 0, 28, None) == 1
 
 
+def test_scan_kernel_rejects_null_arguments():
+    assert pir.lib.pir_scan_kernel(None, None, 1) is None
+
+
 def test_status_strings():
     for code, name in pir.STATUS.items():
         assert pir.lib.pir_status_string(code).decode() == name

@@ -184,6 +184,7 @@ def test_batch1_full_size(ctx):
 
 
 @pytest.mark.parametrize("log2n,K,R,C,B", [(10, 2, 200, 45, 1), (11, 1, 130, 300, 1),
+                                           (10, 2, 512, 45, 1), (10, 1, 2560, 20, 1),
                                            (10, 2, 200, 45, 3), (10, 1, 97, 70, 5),
                                            (10, 1, 97, 70, 17), (10, 2, 300, 41, 33),
                                            (10, 1, 64, 33, 64)])
@@ -208,6 +209,20 @@ def test_every_scan_variant_matches_oracle(ctx, log2n, K, R, C, B):
     out = empty_dev((B, C, 2, K, rg.N))
     ctx.db_mul(db, qd, B, out)
     assert np.array_equal(to_host(out), exp)
+
+
+def test_scan_kernel_names(ctx):
+    """The default batch-1 variant runs the ring kernel when every query chunk's
+    k-block count is a multiple of its depth (R = 512: 8 k-blocks; R = 200: 4),
+    else the grouped kernel (R = 130: 3 k-blocks); B > 1 runs the MFMA kernel."""
+    rg = ring(10, 1)
+    names = {}
+    for R in (512, 200, 130):
+        db = ctx.load_db(rg.pir_params(), synth.db_bytes(R, R, 9, rg.N), R, 9)
+        names[R] = (ctx.scan_kernel(db, 1), ctx.scan_kernel(db, 3))
+        db.free()
+    assert names == {512: ("k_scan_b1r", "k_scan_mfma"), 200: ("k_scan_b1r", "k_scan_mfma"),
+                     130: ("k_scan_b1", "k_scan_mfma")}
 
 
 def test_fused_batch_many_jobs_and_tuning(ctx):
