@@ -263,11 +263,14 @@ pir_status pir_server_info(const pir_server *srv, uint32_t *max_batch, uint32_t 
                            uint32_t *queued, uint32_t *next_chunk);
 
 /* ---- measurement: per-stage kernel time with HIP events (off by default).
- * While enabled, pir_db_mul and pir_answer_batch bracket each stage's launch
- * with a pair of HIP events on the call's stream.  pir_profile_read waits for
+ * While enabled, pir_db_mul and pir_answer_batch time each profiled stage with
+ * a pair of HIP events on the call's stream: the scan's launch records them
+ * itself at the kernel's start and end (no marker commands between kernels);
+ * the other stages record them on the stream around their launches, which
+ * leaves a few microseconds idle between kernels.  pir_profile_read waits for
  * the recorded events and returns the summed elapsed time (ms) and the number
  * of launches of `stage` since profiling was (re-)enabled.  Enabling resets
- * the sums. */
+ * the sums.  Graph captures (pir_plan_create) never record events. */
 typedef enum {
   PIR_STAGE_NTT = 0,  /* forward NTT of queries */
   PIR_STAGE_PACK = 1, /* query transposition into scan tiles */
@@ -277,7 +280,11 @@ typedef enum {
   PIR_N_STAGES = 5
 } pir_stage;
 
+/* enable != 0: time every stage; 0: off. */
 pir_status pir_profile_enable(pir_ctx *ctx, int enable);
+/* Time only the stages whose bit (1 << stage) is set in mask (0: off).
+ * INVALID_ARG for bits at or above PIR_N_STAGES. */
+pir_status pir_profile_stages(pir_ctx *ctx, uint32_t mask);
 pir_status pir_profile_read(pir_ctx *ctx, uint32_t stage, double *total_ms, uint64_t *launches);
 
 #ifdef __cplusplus

@@ -232,20 +232,37 @@ pir_status prime_set(pir_ctx *ctx, const pir_params *p, const DevPrime **out) {
 namespace {
 
 // Brackets one stage launch with HIP events when profiling is on.
+// Times one stage with a pair of HIP events, if that stage is being profiled:
+// recorded on the stream around the stage's launches, or (attached) handed to
+// a launcher through start() / stop() so that the kernel launch itself records
+// them, which puts no marker commands between the kernels.
 struct StageTimer {
   pir_ctx *ctx;
   hipStream_t s;
   pir_ctx::Rec rec{};
-  bool on = false;
-  StageTimer(pir_ctx *c, hipStream_t st, uint32_t stage) : ctx(c), s(st) {
-    if (!ctx->prof) return;
+  bool on = false, attached = false;
+  StageTimer(pir_ctx *c, hipStream_t st, uint32_t stage, bool attach = false)
+      : ctx(c), s(st), attached(attach) {
+    if (!(ctx->prof >> stage & 1u)) return;
     rec.stage = stage;
-    if (hipEventCreate(&rec.a) != hipSuccess || hipEventCreate(&rec.b) != hipSuccess) return;
-    on = hipEventRecord(rec.a, s) == hipSuccess;
+    if (hipEventCreate(&rec.a) != hipSuccess) return;
+    if (hipEventCreate(&rec.b) != hipSuccess) {
+      (void)hipEventDestroy(rec.a);
+      return;
+    }
+    on = attached || hipEventRecord(rec.a, s) == hipSuccess;
+    if (!on) (void)hipEventDestroy(rec.a), (void)hipEventDestroy(rec.b);
   }
+  hipEvent_t start() const { return on ? rec.a : nullptr; }
+  hipEvent_t stop() const { return on ? rec.b : nullptr; }
   ~StageTimer() {
     if (!on) return;
-    if (hipEventRecord(rec.b, s) == hipSuccess) ctx->pending.push_back(rec);
+    if (attached || hipEventRecord(rec.b, s) == hipSuccess) {
+      ctx->pending.push_back(rec);
+    } else {
+      (void)hipEventDestroy(rec.a);
+      (void)hipEventDestroy(rec.b);
+    }
   }
 };
 
@@ -282,8 +299,33 @@ ScanCfg pir::chosen_cfg(const pir_ctx *ctx, const DbDesc &d, uint32_t B) {
 
 namespace {
 
-hipError_t run_scan(pir_ctx *ctx, const ScanJob &job, hipStream_t s) {
-  return launch_scan(&job, 1, chosen_cfg(ctx, job.db, job.B), s);
+// Average duration of `launch` on s: one timed launch (which also warms up)
+// sizes the measurement to about kTuneMs of launches, at least 3 and at most
+// 50, so that variants a few percent apart are told apart also for short scans.
+constexpr float kTuneMs = 5.f;
+
+template <typename F>
+hipError_t time_launches(F launch, hipStream_t s, hipEvent_t e0, hipEvent_t e1, float *avg_ms) {
+  auto timed = [&](int n, float *ms) {
+    hipError_t e = hipEventRecord(e0, s);
+    for (int r = 0; r < n && e == hipSuccess; ++r) e = launch();
+    if (e == hipSuccess) e = hipEventRecord(e1, s);
+    if (e == hipSuccess) e = hipEventSynchronize(e1);
+    if (e == hipSuccess) e = hipEventElapsedTime(ms, e0, e1);
+    return e;
+  };
+  float first = 0.f;
+  hipError_t e = timed(1, &first);
+  if (e != hipSuccess) return e;
+  const int reps = std::min(50, std::max(3, (int)(kTuneMs / std::max(first, 1e-3f)) + 1));
+  float ms = 0.f;
+  e = timed(reps, &ms);
+  *avg_ms = ms / reps;
+  return e;
+}
+
+hipError_t run_scan(pir_ctx *ctx, const ScanJob &job, hipStream_t s, hipEvent_t e0, hipEvent_t e1) {
+  return launch_scan(&job, 1, chosen_cfg(ctx, job.db, job.B), s, e0, e1);
 }
 
 // Key of a fused group of scan jobs: the shapes of its jobs, in order.
@@ -617,8 +659,8 @@ pir_status pir_db_mul(pir_ctx *ctx, const pir_db *db, const uint32_t *query_ntt,
   }
   ScanJob job{d, qatoms, query_ntt, B > 1 ? slot_major : answer_ntt, B, 0, d.K * d.N, 0, 0};
   {
-    StageTimer tm(ctx, s, PIR_STAGE_SCAN);
-    HIP_OR_FAIL(ctx, run_scan(ctx, job, s));
+    StageTimer tm(ctx, s, PIR_STAGE_SCAN, true);
+    HIP_OR_FAIL(ctx, run_scan(ctx, job, s, tm.start(), tm.stop()));
   }
   if (B > 1) {
     StageTimer tm(ctx, s, PIR_STAGE_UNPACK);
@@ -653,8 +695,9 @@ pir_status enqueue_batch(pir_ctx *ctx, const pir_job *jobs, size_t n_jobs, uint8
   // the scans of all jobs: one fused launch per kernel kind
   for (const std::vector<ScanJob> *grp : {&p.b1, &p.mf}) {
     if (grp->empty()) continue;
-    StageTimer tm(ctx, s, PIR_STAGE_SCAN);
-    HIP_OR_FAIL(ctx, launch_scan(grp->data(), grp->size(), group_cfg(ctx, *grp), s));
+    StageTimer tm(ctx, s, PIR_STAGE_SCAN, true);
+    HIP_OR_FAIL(ctx, launch_scan(grp->data(), grp->size(), group_cfg(ctx, *grp), s, tm.start(),
+                                 tm.stop()));
   }
   for (size_t n = 0; n < n_jobs; ++n) {
     const DbDesc &d = jobs[n].db->desc;
@@ -721,8 +764,8 @@ pir_status pir_plan_create(pir_ctx *ctx, const pir_job *jobs, size_t n_jobs, pir
   hipStream_t cs;
   if (hipStreamCreateWithFlags(&cs, hipStreamNonBlocking) != hipSuccess)
     return bail(fail(ctx, PIR_ERR_DEVICE, "hipStreamCreate failed"));
-  const bool prof = ctx->prof;
-  ctx->prof = false;
+  const uint32_t prof = ctx->prof;
+  ctx->prof = 0;
   hipError_t e = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal);
   pir_status qst = PIR_OK;
   if (e == hipSuccess) qst = enqueue_batch(ctx, jobs, n_jobs, (uint8_t *)pl->ws, p, cs);
@@ -783,14 +826,9 @@ pir_status pir_tune_batch(pir_ctx *ctx, const pir_job *jobs, size_t n_jobs, pir_
     float best = 1e30f;
     size_t best_i = 0;
     for (size_t i = 0; i < cands.size(); ++i) {
-      HIP_OR_FAIL(ctx, launch_scan(grp->data(), grp->size(), cands[i], s));
-      HIP_OR_FAIL(ctx, hipEventRecord(e0, s));
-      for (int r = 0; r < 3; ++r) HIP_OR_FAIL(ctx, launch_scan(grp->data(), grp->size(), cands[i], s));
-      HIP_OR_FAIL(ctx, hipEventRecord(e1, s));
-      HIP_OR_FAIL(ctx, hipEventSynchronize(e1));
       float ms = 0.f;
-      HIP_OR_FAIL(ctx, hipEventElapsedTime(&ms, e0, e1));
-      ms /= 3;
+      HIP_OR_FAIL(ctx, time_launches([&] { return launch_scan(grp->data(), grp->size(), cands[i], s); },
+                                     s, e0, e1, &ms));
       char buf[96];
       snprintf(buf, sizeof buf, "%s%zu:%u/%u/%u/%u=%.4f;", grp == &p.b1 ? "b1 " : "mf ", i,
                cands[i].kind, cands[i].jbw, cands[i].unr, cands[i].nt, ms);
@@ -856,16 +894,9 @@ pir_status pir_tune(pir_ctx *ctx, const pir_db *db, uint32_t B, pir_stream strea
   std::string rep;
   float best = 1e30f;
   size_t best_i = 0;
-  const int reps = 3;
   for (size_t i = 0; i < cands.size(); ++i) {
-    HIP_OR_FAIL(ctx, launch_scan(&job, 1, cands[i], s));  // warm-up
-    HIP_OR_FAIL(ctx, hipEventRecord(e0, s));
-    for (int r = 0; r < reps; ++r) HIP_OR_FAIL(ctx, launch_scan(&job, 1, cands[i], s));
-    HIP_OR_FAIL(ctx, hipEventRecord(e1, s));
-    HIP_OR_FAIL(ctx, hipEventSynchronize(e1));
     float ms = 0.f;
-    HIP_OR_FAIL(ctx, hipEventElapsedTime(&ms, e0, e1));
-    ms /= reps;
+    HIP_OR_FAIL(ctx, time_launches([&] { return launch_scan(&job, 1, cands[i], s); }, s, e0, e1, &ms));
     char buf[96];
     snprintf(buf, sizeof buf, "%zu:%u/%u/%u/%u=%.4f;", i, cands[i].kind, cands[i].jbw, cands[i].unr,
              cands[i].nt, ms);
@@ -885,13 +916,18 @@ pir_status pir_tune(pir_ctx *ctx, const pir_db *db, uint32_t B, pir_stream strea
   return PIR_OK;
 }
 
-pir_status pir_profile_enable(pir_ctx *ctx, int enable) {
+pir_status pir_profile_stages(pir_ctx *ctx, uint32_t mask) {
   if (!ctx) return PIR_ERR_INVALID_ARG;
+  if (mask >> PIR_N_STAGES) return fail(ctx, PIR_ERR_INVALID_ARG, "stage mask 0x%x", mask);
   DeviceGuard g(ctx->device);
   profile_drain(ctx);
   for (int i = 0; i < PIR_N_STAGES; ++i) ctx->stage_ms[i] = 0, ctx->stage_n[i] = 0;
-  ctx->prof = enable != 0;
+  ctx->prof = mask;
   return PIR_OK;
+}
+
+pir_status pir_profile_enable(pir_ctx *ctx, int enable) {
+  return pir_profile_stages(ctx, enable ? (1u << PIR_N_STAGES) - 1 : 0u);
 }
 
 pir_status pir_profile_read(pir_ctx *ctx, uint32_t stage, double *total_ms, uint64_t *launches) {

@@ -23,7 +23,7 @@ struct pir_ctx {
   std::map<std::pair<uint32_t, uint32_t>, uint32_t *> tw_tables;  // (log2n, q) -> [4][N]
   std::map<std::vector<uint32_t>, pir::DevPrime *> prime_sets;       // (log2n, q...) -> [K]
   // stage profiling
-  bool prof = false;
+  uint32_t prof = 0;  // bit (1 << stage) set: that stage is timed
   struct Rec {
     uint32_t stage;
     hipEvent_t a, b;

@@ -129,7 +129,10 @@ ScanCfg scan_default_mfma(uint32_t B);
 const char *scan_kernel_name(const ScanCfg &cfg, const DbDesc &d);
 // Scan every job with one variant; jobs are fused into launches of up to 8.
 // kind 0 needs B == 1 for every job, kind 1 any B (query atoms).
-hipError_t launch_scan(const ScanJob *jobs, size_t n, const ScanCfg &cfg, hipStream_t s);
+// e0 / e1 (optional) are recorded by the first launch's start and the last
+// launch's end.
+hipError_t launch_scan(const ScanJob *jobs, size_t n, const ScanCfg &cfg, hipStream_t s,
+                       hipEvent_t e0 = nullptr, hipEvent_t e1 = nullptr);
 
 // Pseudo-random words (bytes < 128, words < 2^28) for autotuner timing runs.
 hipError_t launch_fill_tuning(uint32_t *p, size_t n_words, hipStream_t s);

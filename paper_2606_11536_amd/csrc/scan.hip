@@ -27,6 +27,8 @@
 //    owns JBW x 8 database rows and CBW x 8 query columns; database atoms come
 //    through a register ring D contraction steps deep, query atoms through
 //    double-buffered LDS chunks shared by the block's four waves.
+#include <hip/hip_ext.h>
+
 #include <algorithm>
 
 #include "device_util.h"
@@ -686,8 +688,10 @@ __global__ __launch_bounds__(256, OCC) void k_scan_mfma(const MfArgs args) {
 
 inline uint32_t round8(uint32_t x) { return (x + 7) / 8 * 8; }
 
+// Launchers take optional events that the launch itself records at the
+// kernel's start and end (no separate marker commands on the stream).
 template <int JBW, int UNR, bool NT>
-hipError_t run_b1(const ScanJob *jobs, size_t n, hipStream_t s) {
+hipError_t run_b1(const ScanJob *jobs, size_t n, hipStream_t s, hipEvent_t e0, hipEvent_t e1) {
   B1Args a{};
   uint32_t total = 0;
   for (size_t i = 0; i < n; ++i) {
@@ -705,17 +709,17 @@ hipError_t run_b1(const ScanJob *jobs, size_t n, hipStream_t s) {
   a.n_jobs = (uint32_t)n;
   a.total = total;
   if (total == 0) return hipSuccess;
-  k_scan_b1<JBW, UNR, NT><<<round8(total), 256, 0, s>>>(a);
+  hipExtLaunchKernelGGL(k_scan_b1<JBW, UNR, NT>, dim3(round8(total)), dim3(256), 0, s, e0, e1, 0, a);
   return hipGetLastError();
 }
 
 // The ring kernel when every query chunk's k-block count (kB1Chunk / 2, and
 // half the last chunk's atoms) is a multiple of D; else the grouped kernel.
 template <int JBW, int D, bool NT>
-hipError_t run_b1r(const ScanJob *jobs, size_t n, hipStream_t s) {
+hipError_t run_b1r(const ScanJob *jobs, size_t n, hipStream_t s, hipEvent_t e0, hipEvent_t e1) {
   for (size_t i = 0; i < n; ++i) {
     const uint32_t tail = jobs[i].db.n_ib % kB1Chunk;
-    if ((kB1Chunk / 2) % D != 0 || (tail / 2) % D != 0) return run_b1<JBW, D, NT>(jobs, n, s);
+    if ((kB1Chunk / 2) % D != 0 || (tail / 2) % D != 0) return run_b1<JBW, D, NT>(jobs, n, s, e0, e1);
   }
   B1Args a{};
   uint32_t total = 0;
@@ -734,7 +738,7 @@ hipError_t run_b1r(const ScanJob *jobs, size_t n, hipStream_t s) {
   a.n_jobs = (uint32_t)n;
   a.total = total;
   if (total == 0) return hipSuccess;
-  k_scan_b1r<JBW, D, NT><<<round8(total), 256, 0, s>>>(a);
+  hipExtLaunchKernelGGL(k_scan_b1r<JBW, D, NT>, dim3(round8(total)), dim3(256), 0, s, e0, e1, 0, a);
   return hipGetLastError();
 }
 
@@ -744,7 +748,7 @@ hipError_t run_b1r(const ScanJob *jobs, size_t n, hipStream_t s) {
 constexpr uint32_t kItemsPerBlock = 16, kMinBlocks = 1024;
 
 template <int JBW, int CBW, int D, int OCC>
-hipError_t run_mfma(const ScanJob *jobs, size_t n, hipStream_t s) {
+hipError_t run_mfma(const ScanJob *jobs, size_t n, hipStream_t s, hipEvent_t e0, hipEvent_t e1) {
   MfArgs a{};
   uint32_t total = 0;
   for (size_t i = 0; i < n; ++i) {
@@ -771,11 +775,12 @@ hipError_t run_mfma(const ScanJob *jobs, size_t n, hipStream_t s) {
   a.n_jobs = (uint32_t)n;
   a.total = total;
   if (total == 0) return hipSuccess;
-  k_scan_mfma<JBW, CBW, D, OCC><<<round8(total), 256, 0, s>>>(a);
+  hipExtLaunchKernelGGL(k_scan_mfma<JBW, CBW, D, OCC>, dim3(round8(total)), dim3(256), 0, s, e0, e1,
+                        0, a);
   return hipGetLastError();
 }
 
-typedef hipError_t (*ScanFn)(const ScanJob *, size_t, hipStream_t);
+typedef hipError_t (*ScanFn)(const ScanJob *, size_t, hipStream_t, hipEvent_t, hipEvent_t);
 
 struct Variant {
   ScanCfg cfg;
@@ -839,7 +844,8 @@ const char *scan_kernel_name(const ScanCfg &cfg, const DbDesc &d) {
   return ring ? "k_scan_b1r" : "k_scan_b1";
 }
 
-hipError_t launch_scan(const ScanJob *jobs, size_t n, const ScanCfg &cfg, hipStream_t s) {
+hipError_t launch_scan(const ScanJob *jobs, size_t n, const ScanCfg &cfg, hipStream_t s,
+                       hipEvent_t e0, hipEvent_t e1) {
   for (size_t i = 0; i < n; ++i) {
     const ScanJob &j = jobs[i];
     // the batch-1 kernel reads the NTT-form query; the batched kernel (any B) atoms
@@ -852,7 +858,8 @@ hipError_t launch_scan(const ScanJob *jobs, size_t n, const ScanCfg &cfg, hipStr
     if (v.cfg.kind != cfg.kind || v.cfg.jbw != cfg.jbw || v.cfg.unr != cfg.unr || v.cfg.nt != cfg.nt)
       continue;
     for (size_t i = 0; i < n; i += kMaxFused) {
-      const hipError_t e = v.fn(jobs + i, std::min<size_t>(kMaxFused, n - i), s);
+      const hipError_t e = v.fn(jobs + i, std::min<size_t>(kMaxFused, n - i), s, i == 0 ? e0 : nullptr,
+                                i + kMaxFused >= n ? e1 : nullptr);
       if (e != hipSuccess) return e;
     }
     return hipSuccess;

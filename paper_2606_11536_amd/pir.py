@@ -64,6 +64,7 @@ SIGNATURES = {
     "pir_scan_variants": (ct.c_uint32, [_U32]),
     "pir_scan_select": (ct.c_int, [_P, _P, _U32, _U32]),
     "pir_scan_kernel": (ct.c_char_p, [_P, _P, _U32]),
+    "pir_profile_stages": (ct.c_int, [_P, _U32]),
     "pir_tune": (ct.c_int, [_P, _P, _U32, _P, ct.c_char_p, ct.c_size_t]),
     "pir_tune_batch": (ct.c_int, [_P, ct.POINTER(CJob), ct.c_size_t, _P, ct.c_char_p,
                                   ct.c_size_t]),
@@ -296,9 +297,14 @@ class Context:
                                   len(buf)), self.handle)
         return buf.value.decode()
 
-    def profile(self, enable: bool = True) -> None:
-        """Turn per-stage HIP-event timing on (resets the sums) or off."""
-        _check(lib.pir_profile_enable(self.handle, int(enable)), self.handle)
+    def profile(self, enable: bool = True, stages=None) -> None:
+        """Turn per-stage HIP-event timing on (resets the sums) or off; `stages`
+        (names) limits the timing to those stages."""
+        if stages is None:
+            _check(lib.pir_profile_enable(self.handle, int(enable)), self.handle)
+        else:
+            mask = sum(1 << STAGES[st] for st in stages) if enable else 0
+            _check(lib.pir_profile_stages(self.handle, mask), self.handle)
 
     def profile_read(self, stage: str) -> tuple[float, int]:
         """(summed ms, launches) of a stage since profiling was enabled; waits for the events."""

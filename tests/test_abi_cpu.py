@@ -73,6 +73,7 @@ def test_params_validation_codes():
 
 def test_scan_kernel_rejects_null_arguments():
     assert pir.lib.pir_scan_kernel(None, None, 1) is None
+    assert pir.lib.pir_profile_stages(None, 4) == 1
 
 
 def test_status_strings():

@@ -225,6 +225,35 @@ def test_scan_kernel_names(ctx):
                      130: ("k_scan_b1", "k_scan_mfma")}
 
 
+@pytest.mark.parametrize("B", [1, 3])
+def test_stage_profiling_masks(ctx, B):
+    """Scan-only profiling times every scan launch (events recorded by the
+    launch) and no other stage; full profiling times every stage; the answers
+    are the oracle's either way."""
+    rg = ring(10, 1)
+    R, C = 64, 9
+    raw = synth.db_bytes(41 + B, R, C, rg.N)
+    db = ctx.load_db(rg.pir_params(), raw, R, C)
+    qc = residues(np.random.default_rng(B), (B, R, 2), rg)
+    exp = osc.answer_intt(osc.db_mul(osc.db_ntt(raw, rg.primes, rg.psis),
+                                     osc.query_ntt(qc, rg.primes, rg.psis), rg.primes),
+                          rg.primes, rg.psis)
+    qd = to_dev(qc)
+    out = empty_dev((B, C, 2, 1, rg.N))
+    ctx.profile(True, stages=("scan",))
+    for _ in range(3):
+        ctx.answer_batch([(db, B, qd, out)])
+    scan, ntt = ctx.profile_read("scan"), ctx.profile_read("ntt")
+    assert scan[1] == 3 and scan[0] > 0 and ntt == (0.0, 0)
+    ctx.profile(True)
+    ctx.answer_batch([(db, B, qd, out)])
+    for st in ("ntt", "scan", "intt") + (("pack", "unpack") if B > 1 else ()):
+        assert ctx.profile_read(st)[1] == 1, st
+    ctx.profile(False)
+    assert np.array_equal(to_host(out), exp)
+    db.free()
+
+
 def test_fused_batch_many_jobs_and_tuning(ctx):
     """Eleven jobs over four databases (mixed N, R, C, B, including B = 1): the
     fused scan launches split at eight jobs; every variant choice made by
