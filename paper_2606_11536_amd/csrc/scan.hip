@@ -17,16 +17,18 @@
 // residue in [0, q).
 //
 // Two kernels share the database atoms:
-//  * k_scan_b1 (B = 1): bandwidth-bound streaming.  v_mfma_i32_16x16x64_i8
-//    with 4 database rows x 4 limbs per A operand and the two ciphertext
-//    components x 4 limbs (half the B columns) per B operand.  The block
-//    splits the slot's query limbs straight from the NTT-form query into LDS;
-//    each wave streams its database atoms from HBM with UNR k-blocks of loads
-//    in flight before the first MFMA that needs them.
+//  * k_scan_b1 / k_scan_b1r (B = 1): bandwidth-bound streaming.
+//    v_mfma_i32_16x16x64_i8 with 4 database rows x 4 limbs per A operand and
+//    the two ciphertext components x 4 limbs (half the B columns) per B
+//    operand.  The block splits the slot's query limbs straight from the
+//    NTT-form query into LDS; each wave streams its database atoms from HBM,
+//    in groups of UNR k-blocks (k_scan_b1) or through a register ring that
+//    never drains between row blocks (k_scan_b1r).
 //  * k_scan_mfma (B > 1): v_mfma_i32_32x32x32_i8 over whole atoms.  A wave
 //    owns JBW x 8 database rows and CBW x 8 query columns; database atoms come
 //    through a register ring D contraction steps deep, query atoms through
-//    double-buffered LDS chunks shared by the block's four waves.
+//    LDS chunks shared by the block's four waves (three buffers filled by
+//    LDS DMA, or two filled through staging registers).
 #include <hip/hip_ext.h>
 
 #include <algorithm>
@@ -448,14 +450,28 @@ __device__ __forceinline__ void mf_item(const MfJob &a, uint32_t it, uint32_t wa
 //    requested right after the MFMAs of step s have read ring slot s mod D.
 //    Near the end of an item the ring fills with the next item's first steps,
 //    so the epilogue runs while they are in flight;
-//  * query atoms: LDS buffers of kKCB steps, double-buffered.  Chunk n + 1 is
-//    written and published by a barrier one step before chunk n ends (with
-//    one-step B prefetch; at its last step without), and the global loads of
-//    chunk n + 2 (of this item or the next) are issued right after;
+//  * query atoms: LDS chunks of kKCB steps.  Chunk n + 1 is published by a
+//    barrier one step before chunk n ends (with one-step B prefetch; at its
+//    last step without).  With LDS DMA (three buffers) the loads of chunk
+//    n + 3 (of this item or the next) go out right after that barrier, into
+//    the buffer chunk n used, about two chunks ahead of their use, the same
+//    lead as the ring's; with register staging (two buffers) the loads of
+//    chunk n + 2 go out there and are written to LDS one step before the
+//    next barrier;
 //  * the order inside a step is pinned with scheduling groups, so the
 //    compiler cannot sink the prefetches next to their uses.
 // Every staging condition is wave-uniform, so no load sits under a divergent
 // branch and the memory counters stay exact.
+// One 16-byte-per-lane load from a raw buffer straight into LDS (the 64 lanes
+// fill lds .. lds + 1023).  Issued from inline assembly, so the compiler's
+// wait-count bookkeeping does not see it: every wait for these loads is
+// explicit, and the compiler's own waits for other loads stay correct because
+// vector-memory loads complete in issue order (an unseen newer load can only
+// make a wait longer).
+__device__ __forceinline__ void lds_dma_b128(__amdgpu_buffer_rsrc_t rs, uint32_t off, uint32_t lds) {
+  asm volatile("buffer_load_dwordx4 %0, %1, 0 offen lds" ::"v"(off), "s"(rs), "{m0}"(lds) : "memory");
+}
+
 template <int JBW, int CBW, int D, int OCC>
 __global__ __launch_bounds__(256, OCC) void k_scan_mfma(const MfArgs args) {
   static_assert(D % kKCB == 0 && kKCB >= 2, "ring depth must be a multiple of the query chunk");
@@ -463,7 +479,11 @@ __global__ __launch_bounds__(256, OCC) void k_scan_mfma(const MfArgs args) {
   constexpr uint32_t kBuf = kAtoms * 64;       // uint4 per LDS buffer
   constexpr uint32_t kPer = (kAtoms + 3) / 4;  // chunk atoms per wave
   constexpr int kM = JBW * CBW;                // MFMAs per step
-  __shared__ uint4 sq[2 * kBuf];
+  // Query chunks go straight to LDS through three buffers when they fit
+  // (160 KiB of LDS per CU), else through staging registers and two buffers.
+  constexpr bool kDma = 3 * kBuf * 16 * OCC <= 160 * 1024;
+  static_assert(kAtoms % 4 == 0, "every wave stages the same number of atoms");
+  __shared__ uint4 sq[(kDma ? 3 : 2) * kBuf];
   const uint32_t Lg = xcd_logical(blockIdx.x, gridDim.x);
   if (Lg >= args.total) return;
   const MfJob &a = args.jobs[find_job(args, Lg)];
@@ -472,11 +492,11 @@ __global__ __launch_bounds__(256, OCC) void k_scan_mfma(const MfArgs args) {
   const uint32_t tid = threadIdx.x, lane = tid & 63;
   const uint32_t wave = __builtin_amdgcn_readfirstlane(tid >> 6);
   const uint32_t n_ib = db.n_ib, cbs = a.cb_stride;
-  // Steps per item: n_ib rounded up to the ring depth, and at least two
-  // chunks, so that the staging lookahead of two chunks never reaches past
-  // the next item.  Extra steps meet zero query atoms; their database reads
+  // Steps per item: n_ib rounded up to the ring depth, and at least as many
+  // chunks as the staging looks ahead (two, three with LDS DMA), so that it
+  // never reaches past the next item.  Extra steps meet zero query atoms; their database reads
   // stay within the allocation's tail padding (at most 7 atoms past the end).
-  const uint32_t S = (max(n_ib, 2 * kKCB) + D - 1) / D * D;
+  const uint32_t S = (max(n_ib, (kDma ? 3 : 2) * kKCB) + D - 1) / D * D;
   const uint32_t nc = S / kKCB;  // chunks per item
   const uint32_t lane_off = lane * 16;
 
@@ -522,6 +542,23 @@ __global__ __launch_bounds__(256, OCC) void k_scan_mfma(const MfArgs args) {
         buf[ai * 64 + lane] = make_uint4(st[r].x, st[r].y, st[r].z, st[r].w);
     }
   };
+  // LDS DMA of chunk n into buffer bi, same atoms and zeros as stage_load
+  auto stage_dma = [&](uint32_t n, uint32_t bi) {
+    const bool mine = n < nc;
+    const uint32_t ln = mine ? n : n - nc;
+    const bool live = mine || has_next;
+    const uint32_t cb0 = mine ? cur.cb0 : nxt.cb0, ncb = mine ? cur.ncb : nxt.ncb;
+    const __amdgpu_buffer_rsrc_t rs = mine ? cur.qrs : nxt.qrs;
+#pragma unroll
+    for (uint32_t r = 0; r < kPer; ++r) {
+      const uint32_t ai = wave + 4 * r;
+      const uint32_t kk = ai / CBW, c = ai % CBW, ks = ln * kKCB + kk;
+      const bool ok = live && ks < n_ib && c < ncb;
+      const uint32_t off = (((ks * cbs + cb0 + c) * 64 + lane) * 16) | ((uint32_t)!ok << 31);
+      const uint32_t lds = (uint32_t)(size_t)(sq + (bi * kAtoms + ai) * 64);
+      lds_dma_b128(rs, off, __builtin_amdgcn_readfirstlane(lds));
+    }
+  };
   auto b_read = [&](const uint4 *src, v4i (&bv)[CBW]) {
 #pragma unroll
     for (int c = 0; c < CBW; ++c) {
@@ -530,21 +567,38 @@ __global__ __launch_bounds__(256, OCC) void k_scan_mfma(const MfArgs args) {
     }
   };
 
+  constexpr bool kPf = OCC == 1 || JBW * D * 4 + CBW * 8 <= 64;
+  // LDS DMA: chunk n + 3 is requested right after the barrier that publishes
+  // chunk n + 1, into the buffer chunk n used, and waited for at the barrier
+  // that publishes it.  By then this wave has issued, after it, the ring loads
+  // of two chunks' steps and the next chunk's requests (fewer in the first
+  // chunks); kVmWait is the smallest of these counts.
+  constexpr uint32_t kSpan = D + kKCB - (kPf ? 1 : 0) < 2 * kKCB ? D + kKCB - (kPf ? 1 : 0) : 2 * kKCB;
+  constexpr uint32_t kVmWait = kPer + JBW * kSpan;
+  static_assert(!kDma || 2 * kPer + D * JBW < 64, "wait counts fit the vmcnt field");
   v4i ring[D][JBW];
+  v4i st[kPer];  // staging registers (register staging only)
+  if (kDma) {
+    stage_dma(0, 0);
+    stage_dma(1, 1);
+    stage_dma(2, 2);
+  }
 #pragma unroll
   for (int d = 0; d < D; ++d)
 #pragma unroll
     for (int w = 0; w < JBW; ++w) ring[d][w] = __builtin_nontemporal_load(ring_ptr(w, d));
-  v4i st[kPer];
-  stage_load(0, st);
-  stage_store(sq, st);
-  stage_load(1, st);
-  __syncthreads();
+  if (kDma) {
+    asm volatile("s_waitcnt vmcnt(%0)\n\ts_barrier" ::"n"(2 * kPer + D * JBW) : "memory");
+  } else {
+    stage_load(0, st);
+    stage_store(sq, st);
+    stage_load(1, st);
+    __syncthreads();
+  }
   // Normally the B operands of step s + 1 are read during step s.  Two waves
   // per SIMD with a deep ring have no registers for a second set: each step
   // then reads its own B operands first and the other wave's MFMAs cover the
   // LDS latency.
-  constexpr bool kPf = OCC == 1 || JBW * D * 4 + CBW * 8 <= 64;
   // Step of a chunk that publishes the next chunk.  The buffer it overwrites
   // was last read for the previous chunk's final step; that read comes before
   // the previous chunk's publishing barrier only if it is a prefetch (issued
@@ -558,6 +612,7 @@ __global__ __launch_bounds__(256, OCC) void k_scan_mfma(const MfArgs args) {
 
   const uint32_t ncol = 2 * a.B;
   uint32_t chunk = 0;  // chunks completed by this block (LDS buffer parity)
+  uint32_t b3 = 0;     // chunk mod 3 (LDS DMA buffer)
   for (;;) {
     v16i acc[JBW][CBW];
 #pragma unroll
@@ -569,8 +624,10 @@ __global__ __launch_bounds__(256, OCC) void k_scan_mfma(const MfArgs args) {
 #pragma unroll
       for (int d = 0; d < D; ++d) {
         const int kk = d % (int)kKCB;
-        const uint4 *bcur_buf = sq + (chunk & 1) * kBuf;
-        const uint4 *bnxt_buf = sq + ((chunk + 1) & 1) * kBuf;
+        const uint32_t bc = kDma ? b3 : chunk & 1;
+        const uint32_t bn = kDma ? (b3 == 2 ? 0 : b3 + 1) : (chunk + 1) & 1;
+        const uint4 *bcur_buf = sq + bc * kBuf;
+        const uint4 *bnxt_buf = sq + bn * kBuf;
         // MFMAs of tiles [i0, i1) of this step (tile i = row block i / CBW,
         // column block i % CBW)
         auto mfmas = [&](int i0, int i1) {
@@ -589,8 +646,15 @@ __global__ __launch_bounds__(256, OCC) void k_scan_mfma(const MfArgs args) {
           // so nothing else keeps the compiler from sinking it past)
 #pragma unroll
           for (int i = 0; i < kPre; ++i) asm volatile("" : "+a"(acc[i / CBW][i % CBW]));
-          __syncthreads();
-          stage_load(cl + 2, st);
+          if (kDma) {
+            // every LDS read of this wave is done (the MFMAs above consumed
+            // them), so buffer bc is free once all waves pass the barrier
+            asm volatile("s_waitcnt vmcnt(%0) lgkmcnt(0)\n\ts_barrier" ::"n"(kVmWait) : "memory");
+            stage_dma(cl + 3, bc);
+          } else {
+            __syncthreads();
+            stage_load(cl + 2, st);
+          }
           __builtin_amdgcn_sched_barrier(0);
           b_read(bnxt_buf, bnext);
           mfmas(kPre, kM);
@@ -603,7 +667,7 @@ __global__ __launch_bounds__(256, OCC) void k_scan_mfma(const MfArgs args) {
           // B operands of the next step (this chunk)
           b_read(bcur_buf + (kk + 1) * CBW * 64, bnext);
           mfmas(0, kM);
-          if (kk == kPub) {
+          if (!kDma && kk == kPub) {
             // publish chunk + 1: the staging stores ride between this step's
             // MFMAs, after its next-step B reads
             stage_store(sq + ((chunk + 1) & 1) * kBuf, st);
@@ -612,7 +676,7 @@ __global__ __launch_bounds__(256, OCC) void k_scan_mfma(const MfArgs args) {
           for (int i = 0; i < kM; ++i) {
             __builtin_amdgcn_sched_group_barrier(kSgMfma, 1, 0);
             if (i < CBW) __builtin_amdgcn_sched_group_barrier(kSgDsRead, 1, 0);
-            else if (kk == kPub && i - CBW < (int)kPer)
+            else if (!kDma && kk == kPub && i - CBW < (int)kPer)
               __builtin_amdgcn_sched_group_barrier(kSgDsWrite, 1, 0);
           }
         } else {
@@ -626,16 +690,24 @@ __global__ __launch_bounds__(256, OCC) void k_scan_mfma(const MfArgs args) {
           ring[d][w] = __builtin_nontemporal_load(ring_ptr(w, ks0 + D + d));
         __builtin_amdgcn_sched_group_barrier(kSgVmemRead, JBW, 0);
         if (!kPf && kk == kPub) {
-          // publish chunk + 1 (after this step's ring loads), then fetch
-          // chunk + 2 into the staging registers
-          __builtin_amdgcn_sched_group_barrier(kSgDsWrite, kPer, 0);
-          stage_store(sq + ((chunk + 1) & 1) * kBuf, st);
-          __syncthreads();
-          stage_load(cl + 2, st);
-          // keep the staging loads here, a chunk ahead of their use
-          __builtin_amdgcn_sched_barrier(0);
+          if (kDma) {
+            // publish chunk + 1 after this step's reads and ring loads
+            __builtin_amdgcn_sched_barrier(0);
+            asm volatile("s_waitcnt vmcnt(%0) lgkmcnt(0)\n\ts_barrier" ::"n"(kVmWait) : "memory");
+            stage_dma(cl + 3, bc);
+            __builtin_amdgcn_sched_barrier(0);
+          } else {
+            // publish chunk + 1 (after this step's ring loads), then fetch
+            // chunk + 2 into the staging registers
+            __builtin_amdgcn_sched_group_barrier(kSgDsWrite, kPer, 0);
+            stage_store(sq + ((chunk + 1) & 1) * kBuf, st);
+            __syncthreads();
+            stage_load(cl + 2, st);
+            // keep the staging loads here, a chunk ahead of their use
+            __builtin_amdgcn_sched_barrier(0);
+          }
         }
-        if (kk == (int)kKCB - 1) ++chunk, ++cl;
+        if (kk == (int)kKCB - 1) ++chunk, ++cl, b3 = b3 == 2 ? 0 : b3 + 1;
         if (kPf) {
 #pragma unroll
           for (int c = 0; c < CBW; ++c) bcur[c] = bnext[c];
@@ -677,13 +749,16 @@ __global__ __launch_bounds__(256, OCC) void k_scan_mfma(const MfArgs args) {
       }
     }
     if (!has_next) break;
-    // the ring, the published chunk and the staging registers already hold
-    // the next item's first steps
+    // the ring, the published chunk and the staged chunks already hold the
+    // next item's first steps
     it += a.n_blocks;
     cur = nxt;
     has_next = it + a.n_blocks < a.n_items;
     if (has_next) mf_item<JBW, CBW>(a, it + a.n_blocks, wave, nxt);
   }
+  // LDS DMA requests past the last chunk are still in flight: the wave may
+  // not end before they have written this workgroup's LDS
+  if (kDma) asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
 }
 
 inline uint32_t round8(uint32_t x) { return (x + 7) / 8 * 8; }
