@@ -17,6 +17,8 @@ Modules
 ``scan``    plaintext lift + NTT of the database (Sec. 2.4), the
             first-dimension scan by its definition (Sec. 3.2 poly-HE folding,
             Sec. 4 INT32 modular GEMM), and a Freivalds full-output check.
+``modswitch`` modulus switching of answers from Q down to 2^t (Sec. 4.3,
+            App. D.5) and decryption at the reduced modulus.
 
 All arithmetic is on exact integers (Python ints, or numpy uint64/int64 with
 every intermediate bounded below 2**63); nothing is approximated.
