@@ -45,6 +45,9 @@ WORKLOADS = {
 # serving: device-resident 16 GiB raw database, Poisson arrivals
 SERVE = dict(log2n=11, K=2, R=4096, C=2048, max_batch=128, n_chunks=64, pool=16,
              rates=[50, 100, 200, 500, 1000, 2000])
+# answer drain with modulus switching: the answers of one batch of 32 queries over
+# 1024 columns (32 x 1024 x 2 polynomials), switched to 2^29
+DRAIN = dict(log2n=11, K=2, polys=32 * 1024 * 2, bits=29)
 # three databases of uneven shape in one batch: (log2n, K, R, C)
 MULTIDB = [(12, 2, 1024, 512), (11, 2, 3000, 700), (11, 2, 256, 4096)]
 
@@ -296,6 +299,83 @@ def srv_max(cfg) -> int:
     return cfg["max_batch"]
 
 
+def drain(args) -> dict:
+    """Inverse NTT fused with modulus switching over one batch's answers, against the
+    plain inverse NTT of the same residues."""
+    import torch
+
+    from paper_2606_11536_amd import pir
+    log2n, K, P, bits = DRAIN["log2n"], DRAIN["K"], DRAIN["polys"], DRAIN["bits"]
+    N = 1 << log2n
+    primes = pir.find_primes(log2n, K, 28)
+    params = pir.Params(log2n, primes, 8)
+    cpu = None
+    if not args.no_cpu_baseline:
+        from oracle import modswitch as oms
+        from oracle import params as op
+        psis = [op.psi_min(N, q) for q in op.ntt_primes(N, K)]
+        sample = 1024
+        rng = np.random.default_rng(args.seed)
+        hat = np.stack([rng.integers(0, q, (sample, N), dtype=np.uint64) for q in primes], axis=1)
+        t = time.perf_counter()
+        oms.intt_switch(hat, op.ntt_primes(N, K), psis, bits)
+        sec = time.perf_counter() - t
+        cpu = {"value": round(sample * (K + 1) * N * 4 / sec / 1e9, 6), "unit": "GB/s", "cores": 1,
+               "kind": "oracle", "sample": f"oracle INTT + switch of {sample} polynomials "
+                                           f"({K} primes, N={N}) in {sec:.2f} s on one core"}
+    ctx = pir.Context(0)
+    gen = torch.Generator(device="cuda").manual_seed(args.seed)
+    src = torch.empty((P, K, N), dtype=torch.int32, device="cuda")
+    for k, q in enumerate(primes):
+        src[:, k].copy_(torch.randint(0, q, (P, N), generator=gen, device="cuda",
+                                      dtype=torch.int64).to(torch.int32))
+    out = torch.empty((P, N), dtype=torch.int32, device="cuda")
+    plain = src.clone()
+    for _ in range(args.warmup):
+        ctx.intt_modswitch(params, src, out, bits)
+    torch.cuda.synchronize()
+    ctx.profile(True, stages=("intt",))
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        ctx.intt_modswitch(params, src, out, bits)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    ms, n = ctx.profile_read("intt")
+    fused_ms = ms / max(n, 1)
+    ctx.profile(False)
+    # the plain inverse NTT (in place; the values do not affect timing), timed with
+    # events on the stream both calls use
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(args.steps):
+        ctx.intt(params, plain)
+    e1.record()
+    torch.cuda.synchronize()
+    plain_ms = e0.elapsed_time(e1) / args.steps
+    in_b, out_b = P * K * N * 4, P * N * 4
+    achieved = (in_b + out_b) / (fused_ms * 1e-3) / 1e9
+    res = {
+        "metric": "answer drain GB/s (inverse NTT fused with modulus switching to 2^29)",
+        "value": round((in_b + out_b) * args.steps / wall / 1e9, 3), "unit": "GB/s",
+        "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": round(wall * 1e3 / args.steps, 5), "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "f64", "data": "synthetic",
+        "config": {"workload": f"answers of one batch of 32 queries x 1024 columns: {P} "
+                               f"polynomials, N={N}, {K} primes < 2^28, switched to 2^{bits}",
+                   "polys": P, "N": N, "primes": primes, "bits": bits},
+        "fused_ms": round(fused_ms, 5), "plain_intt_ms": round(plain_ms, 5),
+        "roofline": {"bound": "hbm", "kernel": "k_intt_switch", "achieved": round(achieved, 2),
+                     "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
+                     "traffic": None, "alg_bytes_per_launch": in_b + out_b,
+                     "avg_launch_ms": round(fused_ms, 5),
+                     "note": "the two inverse NTTs per polynomial are fp64-issue-bound"},
+    }
+    if cpu is not None:
+        res["cpu_baseline"] = cpu
+    ctx.close()
+    return res
+
+
 def multidb(args) -> dict:
     """Three uneven databases, 1..64 queries each, one fused batch, HIP-graph replays."""
     import torch
@@ -360,7 +440,7 @@ def main() -> int:
     ap.add_argument("--steps", type=int, default=50)
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--workload", default="batch1",
-                    choices=sorted(WORKLOADS) + ["serving", "multidb"])
+                    choices=sorted(WORKLOADS) + ["serving", "multidb", "drain"])
     ap.add_argument("--serve-seconds", type=float, default=3.0)
     ap.add_argument("--serve-max-requests", type=int, default=1500)
     ap.add_argument("--seed", type=int, default=0)
@@ -376,8 +456,9 @@ def main() -> int:
     if args.calibrate_copy:
         calibrate_copy()
         return 0
-    if args.workload in ("serving", "multidb"):
-        print(json.dumps(serve(args) if args.workload == "serving" else multidb(args)), flush=True)
+    if args.workload in ("serving", "multidb", "drain"):
+        fn = {"serving": serve, "multidb": multidb, "drain": drain}[args.workload]
+        print(json.dumps(fn(args)), flush=True)
         return 0
 
     log2n, K, R, C, B = WORKLOADS[args.workload]

@@ -114,7 +114,7 @@ size_t pir_ctx_device_bytes(const pir_ctx *ctx);
  * calls of that size allocate nothing.  Synchronizes the device when it grows. */
 pir_status pir_ctx_reserve(pir_ctx *ctx, size_t bytes);
 
-/* ---- a1: offline database transform (Sec. 2.4 plaintext bloating; Sec. 3.2
+/* ---- offline database transform (Sec. 2.4 plaintext bloating; Sec. 3.2
  * step 5; Sec. 4.2 layout transposition; Sec. 4.3 fused RNS decomposition).
  * Lifts every byte of `raw` ([R][C][N] uint8, row-major: row i, column j,
  * coefficient n) into Z_{q_k} for every prime, applies the forward NTT, and
@@ -137,14 +137,14 @@ pir_status pir_db_info(const pir_db *db, pir_params *params, uint32_t *R, uint32
 
 /* Read back NTT-form database polynomials in canonical layout: rows
  * [i0, i0+ni) x columns [j0, j0+nj) into `out` (device, [ni][nj][K][N] uint32).
- * For checking a1 against an independent transform. */
+ * For checking the offline transform against an independent one. */
 pir_status pir_db_read_ntt(pir_ctx *ctx, const pir_db *db, uint32_t i0, uint32_t ni,
                            uint32_t j0, uint32_t nj, uint32_t *out, pir_stream stream);
 
 /* Release a database's device memory (waits for the device). */
 void pir_db_free(pir_db *db);
 
-/* ---- a2/a4: forward / inverse negacyclic NTT (Sec. 2.3; Sec. 4.3),
+/* ---- forward / inverse negacyclic NTT of queries and answers (Sec. 2.3; Sec. 4.3),
  * in place on `polys` (device, [n_polys][K][N] uint32, residues < q_k).
  * The inverse includes N^-1.  Values >= q_k give unspecified results (never an
  * out-of-bounds access). */
@@ -153,7 +153,22 @@ pir_status pir_ntt(pir_ctx *ctx, const pir_params *params, uint32_t *polys, size
 pir_status pir_intt(pir_ctx *ctx, const pir_params *params, uint32_t *polys, size_t n_polys,
                     pir_stream stream);
 
-/* ---- a3: the scan in NTT form (Sec. 3.2 step 6; Sec. 4 INT32 modular GEMM).
+/* ---- answer drain with modulus switching: inverse NTT fused with it (Sec. 4.3 fuses the
+ * modulus reduction into the inverse NTT; Sec. 3.6 ends the online answer with
+ * it; App. D.5 bounds its error).  For each of n_polys answer polynomials in
+ * NTT form, answer_ntt[p][k][t] (device, [n_polys][K][N] uint32 residues in
+ * [0, q_k), K = params->n_primes), the inverse NTT per prime gives residues
+ * of coefficient x in [0, Q), Q = q_0 q_1 (or q_0); out[p][t] (device,
+ * [n_polys][N] uint32) receives the nearest integer to x * 2^bits / Q,
+ * reduced mod 2^bits (Q is odd, so there are no ties).  The paper's target
+ * is bits = 29.  answer_ntt is not modified; out must not overlap it.
+ * Asynchronous on `stream`.  Errors: INVALID_ARG (NULL buffers with
+ * n_polys > 0, bits outside [1, 32], bad params), UNSUPPORTED (more than two
+ * primes).  Timed as the INTT stage when profiling is on. */
+pir_status pir_intt_modswitch(pir_ctx *ctx, const pir_params *params, const uint32_t *answer_ntt,
+                              size_t n_polys, uint32_t bits, uint32_t *out, pir_stream stream);
+
+/* ---- the scan in NTT form (Sec. 3.2 step 6; Sec. 4 INT32 modular GEMM).
  * query_ntt: device [B][R][2][K][N], NTT form; answer_ntt: device
  * [B][C][2][K][N], NTT form, fully overwritten:
  *   answer[b][j][c][k][t] = sum_i D_k[i][j][t] * query[b][i][c][k][t] (mod q_k).
@@ -164,7 +179,7 @@ pir_status pir_intt(pir_ctx *ctx, const pir_params *params, uint32_t *polys, siz
 pir_status pir_db_mul(pir_ctx *ctx, const pir_db *db, const uint32_t *query_ntt, uint32_t B,
                       uint32_t *answer_ntt, pir_stream stream);
 
-/* ---- a5: fused batch over several databases (Sec. 2.5 multi-client
+/* ---- fused batch over several databases (Sec. 2.5 multi-client
  * batching; Sec. 4.4 stream-wise buffering).  For every job: forward NTT of
  * its queries, the scan, inverse NTT of its answers -- coefficient form in and
  * out.  Jobs may name different databases (different N, R, C); the scans of
@@ -180,7 +195,7 @@ typedef struct {
 pir_status pir_answer_batch(pir_ctx *ctx, const pir_job *jobs, size_t n_jobs,
                             pir_stream stream);
 
-/* ---- a5 steady state: a job list captured once into a HIP graph.
+/* ---- batch steady state: a job list captured once into a HIP graph.
  * pir_plan_create records what pir_answer_batch(jobs) enqueues (all kernel
  * launches, with the scan variants chosen at that moment) into a graph with
  * a workspace of its own; pir_plan_launch replays it on `stream` with no
@@ -194,7 +209,7 @@ pir_status pir_plan_create(pir_ctx *ctx, const pir_job *jobs, size_t n_jobs, pir
 pir_status pir_plan_launch(pir_plan *plan, pir_stream stream);
 void pir_plan_destroy(pir_plan *plan);
 
-/* ---- tuning of the scan (a3).  Several kernel variants compute the same
+/* ---- tuning of the scan.  Several kernel variants compute the same
  * exact result with different tile shapes, unroll depths and load policies.
  * The context remembers one variant per (N, K, R, C, B); without a choice a
  * fixed default is used.  Results never depend on the variant. */
@@ -226,7 +241,7 @@ pir_status pir_tune(pir_ctx *ctx, const pir_db *db, uint32_t B, pir_stream strea
 pir_status pir_tune_batch(pir_ctx *ctx, const pir_job *jobs, size_t n_jobs, pir_stream stream,
                           char *report, size_t report_len);
 
-/* ---- a6: continuous-batching server (Sec. 2.5 multi-client batching;
+/* ---- continuous-batching server (Sec. 2.5 multi-client batching;
  * Sec. 4.4 stream-wise buffering).  The database's K*N (prime, slot) pairs are
  * cut into n_chunks ranges scanned round-robin, one range per step.  A query
  * is admitted at a step boundary into a free column slot (forward NTT and

@@ -637,6 +637,28 @@ pir_status pir_intt(pir_ctx *ctx, const pir_params *params, uint32_t *polys, siz
   return ntt_common(ctx, params, polys, n_polys, stream, true);
 }
 
+pir_status pir_intt_modswitch(pir_ctx *ctx, const pir_params *params, const uint32_t *answer_ntt,
+                              size_t n_polys, uint32_t bits, uint32_t *out, pir_stream stream) {
+  if (!ctx) return PIR_ERR_INVALID_ARG;
+  pir_status st = check_params(ctx, params);
+  if (st != PIR_OK) return st;
+  if (params->n_primes > 2)
+    return fail(ctx, PIR_ERR_UNSUPPORTED, "modulus switching takes 1 or 2 primes, not %u",
+                params->n_primes);
+  if (bits < 1 || bits > 32) return fail(ctx, PIR_ERR_INVALID_ARG, "bits=%u not in [1, 32]", bits);
+  if ((!answer_ntt || !out) && n_polys) return fail(ctx, PIR_ERR_INVALID_ARG, "null buffer");
+  if (n_polys > (size_t)0x7fffffff) return fail(ctx, PIR_ERR_INVALID_ARG, "too many polynomials");
+  if (n_polys == 0) return PIR_OK;
+  DeviceGuard g(ctx->device);
+  const DevPrime *primes = nullptr;
+  if ((st = prime_set(ctx, params, &primes)) != PIR_OK) return st;
+  hipStream_t s = (hipStream_t)stream;
+  StageTimer tm(ctx, s, PIR_STAGE_INTT);
+  HIP_OR_FAIL(ctx, launch_intt_switch(answer_ntt, out, n_polys, params->n_primes, params->primes,
+                                      params->log2_n, primes, bits, s));
+  return PIR_OK;
+}
+
 pir_status pir_db_mul(pir_ctx *ctx, const pir_db *db, const uint32_t *query_ntt, uint32_t B,
                       uint32_t *answer_ntt, pir_stream stream) {
   if (!ctx) return PIR_ERR_INVALID_ARG;

@@ -22,6 +22,8 @@
 // inverse stages at most double (|x| < 2^12 q < 2^41), so every product
 // stays below 2^70 and every sum is an exact integer below 2^53.  Each value
 // is reduced to [0, q) once at the end.
+#include <cmath>
+
 #include "device_util.h"
 #include "pir_internal.h"
 
@@ -187,6 +189,81 @@ __global__ __launch_bounds__(kThreads) void k_lift_ntt(const uint8_t *__restrict
   for (int e = 0; e < G::E; ++e) o[ridx<LOGN, false, LAST>(tid, e)] = y[e];
 }
 
+// Modulus switching (Sec. 4.3 fuses it with the inverse NTT; App. D.5): the
+// coefficient x in [0, Q) with residues x0 mod q0 (and x1 mod q1) becomes the
+// nearest integer to x 2^bits / Q, reduced mod 2^bits.
+//  * CRT (Garner): y = (x1 - x0) q0^-1 mod q1, x = x0 + q0 y < Q < 2^56,
+//    with the exact fp64 product of mulmod_f64;
+//  * k = rint(x * (2^bits / Q)) in fp64 is within one of the nearest integer:
+//    its error is below 2^-19 on a value below 2^32;
+//  * the residual r = x 2^bits - k Q is computed in wrapping 64-bit integer
+//    arithmetic, exact because |r| < 2 Q < 2^58; k moves by one when |2r| > Q.
+//    2r = +-Q would be a tie, impossible for odd Q.
+struct MsArgs {
+  uint64_t Q;          // q0 q1 (q0 for one prime)
+  double scale;        // 2^bits / Q
+  double q1d, inv_q1;  // q1 and 1 / q1
+  double c;            // q0^-1 mod q1
+  uint32_t q0, q1, bits, mask;
+};
+
+template <bool TWO>
+__device__ __forceinline__ uint32_t mod_switch(uint32_t x0, uint32_t x1, const MsArgs &m) {
+  uint64_t x = x0;
+  if constexpr (TWO) {
+    const uint32_t x0r = x0 >= m.q1 ? x0 - m.q1 : x0;  // x0 < q0 < 2 q1
+    uint32_t d = x1 + m.q1 - x0r;                       // < 2 q1
+    d = d >= m.q1 ? d - m.q1 : d;
+    const double r = mulmod_f64((double)d, m.c, m.q1d, m.inv_q1);  // |r| < 0.51 q1
+    const uint32_t y = (uint32_t)(int)(r < 0.0 ? r + m.q1d : r);
+    x += (uint64_t)m.q0 * y;
+  }
+  int64_t k = (int64_t)__builtin_rint((double)x * m.scale);
+  const int64_t r = (int64_t)((x << m.bits) - (uint64_t)k * m.Q);
+  const int64_t Q = (int64_t)m.Q;
+  if (2 * r > Q) ++k;
+  else if (2 * r < -Q) --k;
+  return (uint32_t)k & m.mask;
+}
+
+// One block per answer polynomial [K][N] (K = 1 or 2): both residue rows are
+// loaded up front, inverse-transformed one after the other in the same LDS,
+// and every coefficient is switched on its way out: [N] words, no
+// intermediate coefficient form in HBM.
+template <int LOGN, bool TWO>
+__global__ __launch_bounds__(kThreads) void k_intt_switch(const uint32_t *__restrict__ src,
+                                                          uint32_t *__restrict__ dst,
+                                                          const DevPrime *__restrict__ primes,
+                                                          const MsArgs m) {
+  using G = Geo<LOGN>;
+  __shared__ double sm[G::N];
+  const uint32_t tid = threadIdx.x;
+  const size_t poly = blockIdx.x;
+  const uint32_t *in = src + poly * (TWO ? 2 : 1) * G::N;
+  uint32_t u0[G::E], u1[G::E];
+#pragma unroll
+  for (int e = 0; e < G::E; ++e) {
+    u0[e] = in[ridx<LOGN, true, 0>(tid, e)];
+    if constexpr (TWO) u1[e] = in[G::N + ridx<LOGN, true, 0>(tid, e)];
+  }
+  double x[G::E];
+  uint32_t y0[G::E], y1[G::E];
+#pragma unroll
+  for (int e = 0; e < G::E; ++e) x[e] = (double)u0[e];
+  transform<LOGN, true>(x, y0, tid, sm, primes[0]);
+  if constexpr (TWO) {
+    __syncthreads();  // the first transform's last LDS reads are done
+#pragma unroll
+    for (int e = 0; e < G::E; ++e) x[e] = (double)u1[e];
+    transform<LOGN, true>(x, y1, tid, sm, primes[1]);
+  }
+  constexpr int LAST = G::ROUNDS - 1;
+  uint32_t *out = dst + poly * G::N;
+#pragma unroll
+  for (int e = 0; e < G::E; ++e)
+    out[ridx<LOGN, true, LAST>(tid, e)] = mod_switch<TWO>(y0[e], TWO ? y1[e] : 0u, m);
+}
+
 template <bool INV>
 hipError_t ntt_rows_dispatch(const uint32_t *src, uint32_t *dst, size_t n_rows, uint32_t K,
                              uint32_t log2n, const DevPrime *primes, hipStream_t s) {
@@ -212,6 +289,47 @@ hipError_t launch_ntt(uint32_t *data, size_t n_rows, uint32_t K, uint32_t log2n,
 hipError_t launch_ntt_copy(const uint32_t *src, uint32_t *dst, size_t n_rows, uint32_t K,
                            uint32_t log2n, const DevPrime *primes, hipStream_t s) {
   return ntt_rows_dispatch<false>(src, dst, n_rows, K, log2n, primes, s);
+}
+
+hipError_t launch_intt_switch(const uint32_t *src, uint32_t *dst, size_t n_polys, uint32_t K,
+                              const uint32_t *q, uint32_t log2n, const DevPrime *primes,
+                              uint32_t bits, hipStream_t s) {
+  if (n_polys == 0) return hipSuccess;
+  if (K < 1 || K > 2 || bits < 1 || bits > 32) return hipErrorInvalidValue;
+  MsArgs m{};
+  m.q0 = q[0];
+  m.q1 = K == 2 ? q[1] : 1;
+  m.Q = K == 2 ? (uint64_t)q[0] * q[1] : q[0];
+  m.scale = std::ldexp(1.0, (int)bits) / (double)m.Q;
+  m.q1d = (double)m.q1;
+  m.inv_q1 = 1.0 / m.q1d;
+  // q0^-1 mod q1 by the extended Euclidean algorithm
+  int64_t r0 = m.q1, r1 = m.q0 % m.q1, t0 = 0, t1 = 1;
+  while (r1 != 0) {
+    const int64_t qt = r0 / r1, r2 = r0 - qt * r1, t2 = t0 - qt * t1;
+    r0 = r1, r1 = r2, t0 = t1, t1 = t2;
+  }
+  m.c = (double)(K == 2 ? (uint32_t)((t0 % (int64_t)m.q1 + m.q1) % m.q1) : 0u);
+  m.bits = bits;
+  m.mask = bits == 32 ? 0xffffffffu : (1u << bits) - 1;
+  const dim3 grid((unsigned)n_polys), block(kThreads);
+  const bool two = K == 2;
+  switch (log2n) {
+    case 10:
+      if (two) k_intt_switch<10, true><<<grid, block, 0, s>>>(src, dst, primes, m);
+      else k_intt_switch<10, false><<<grid, block, 0, s>>>(src, dst, primes, m);
+      break;
+    case 11:
+      if (two) k_intt_switch<11, true><<<grid, block, 0, s>>>(src, dst, primes, m);
+      else k_intt_switch<11, false><<<grid, block, 0, s>>>(src, dst, primes, m);
+      break;
+    case 12:
+      if (two) k_intt_switch<12, true><<<grid, block, 0, s>>>(src, dst, primes, m);
+      else k_intt_switch<12, false><<<grid, block, 0, s>>>(src, dst, primes, m);
+      break;
+    default: return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
 }
 
 hipError_t launch_lift_ntt(const uint8_t *raw, uint32_t *out, uint32_t S, uint32_t s_valid,

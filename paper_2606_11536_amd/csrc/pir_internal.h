@@ -73,6 +73,11 @@ struct DbDesc {
 hipError_t launch_ntt(uint32_t *data, size_t n_rows, uint32_t K, uint32_t log2n,
                       const DevPrime *primes, bool inverse, hipStream_t s);
 // Out-of-place forward NTT: src and dst both [n_rows][N] (row r -> prime r % K).
+// Fused inverse NTT and modulus switching of n_polys answer polynomials
+// [K][N] (K = 1 or 2, host primes q[K]) into [N] words mod 2^bits each.
+hipError_t launch_intt_switch(const uint32_t *src, uint32_t *dst, size_t n_polys, uint32_t K,
+                              const uint32_t *q, uint32_t log2n, const DevPrime *primes,
+                              uint32_t bits, hipStream_t s);
 hipError_t launch_ntt_copy(const uint32_t *src, uint32_t *dst, size_t n_rows, uint32_t K,
                            uint32_t log2n, const DevPrime *primes, hipStream_t s);
 // Lift + forward NTT of a slab of raw database rows: raw [S][C][N] uint8 ->

@@ -59,6 +59,7 @@ SIGNATURES = {
     "pir_db_free": (None, [_P]),
     "pir_ntt": (ct.c_int, [_P, ct.POINTER(CParams), _P, ct.c_size_t, _P]),
     "pir_intt": (ct.c_int, [_P, ct.POINTER(CParams), _P, ct.c_size_t, _P]),
+    "pir_intt_modswitch": (ct.c_int, [_P, ct.POINTER(CParams), _P, ct.c_size_t, _U32, _P, _P]),
     "pir_db_mul": (ct.c_int, [_P, _P, _P, _U32, _P, _P]),
     "pir_answer_batch": (ct.c_int, [_P, ct.POINTER(CJob), ct.c_size_t, _P]),
     "pir_scan_variants": (ct.c_uint32, [_U32]),
@@ -268,6 +269,14 @@ class Context:
         n = polys.numel() // (params.K * params.N) if n_polys is None else n_polys
         _check(lib.pir_intt(self.handle, ct.byref(params.c()), _ptr(polys), n, _stream(stream)),
                self.handle)
+
+    def intt_modswitch(self, params: Params, answer_ntt, out, bits: int = 29,
+                       n_polys: int | None = None, stream=None) -> None:
+        """Inverse NTT fused with modulus switching: answer_ntt [P][K][N] (NTT form,
+        device) -> out [P][N] (device), nearest integer to x 2^bits / Q mod 2^bits."""
+        n = answer_ntt.numel() // (params.K * params.N) if n_polys is None else n_polys
+        _check(lib.pir_intt_modswitch(self.handle, ct.byref(params.c()), _ptr(answer_ntt), n,
+                                      bits, _ptr(out), _stream(stream)), self.handle)
 
     def db_mul(self, db: Database, query_ntt, B: int, answer_ntt, stream=None) -> None:
         """NTT-form scan: query [B][R][2][K][N] -> answer [B][C][2][K][N] (device tensors)."""
