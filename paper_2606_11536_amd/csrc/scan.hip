@@ -328,49 +328,49 @@ __global__ __launch_bounds__(256) void k_scan_b1r(const B1Args args) {
 #pragma unroll
     for (int w = 0; w < JBW; ++w) {
       if ((uint32_t)w < nw) {
-      auto mma = [&](const v4i &x0, const v4i &x1, uint32_t kb) {
-        const uint4 x = sq4[(2 * kb + (g >> 1)) * 16 + (g & 1) * 8 + (m & 7)];
-        const v4i bv = bzero ? v4i{0, 0, 0, 0} : v4i{(int)x.x, (int)x.y, (int)x.z, (int)x.w};
-        acc[w][0] = __builtin_amdgcn_mfma_i32_16x16x64_i8(x0, bv, acc[w][0], 0, 0, 0);
-        acc[w][1] = __builtin_amdgcn_mfma_i32_16x16x64_i8(x1, bv, acc[w][1], 0, 0, 0);
-      };
-      const uint8_t *base = row_ptr(w, ib0);
-      uint32_t kb0 = 0;
-      for (; kb0 + D < nkb; kb0 += D) {
+        auto mma = [&](const v4i &x0, const v4i &x1, uint32_t kb) {
+          const uint4 x = sq4[(2 * kb + (g >> 1)) * 16 + (g & 1) * 8 + (m & 7)];
+          const v4i bv = bzero ? v4i{0, 0, 0, 0} : v4i{(int)x.x, (int)x.y, (int)x.z, (int)x.w};
+          acc[w][0] = __builtin_amdgcn_mfma_i32_16x16x64_i8(x0, bv, acc[w][0], 0, 0, 0);
+          acc[w][1] = __builtin_amdgcn_mfma_i32_16x16x64_i8(x1, bv, acc[w][1], 0, 0, 0);
+        };
+        const uint8_t *base = row_ptr(w, ib0);
+        uint32_t kb0 = 0;
+        for (; kb0 + D < nkb; kb0 += D) {
 #pragma unroll
-        for (int d = 0; d < D; ++d) {
-          mma(r0[d], r1[d], kb0 + d);
-          r0[d] = load_atom16<NT>(base + (size_t)(kb0 + D + d) * 2048);
-          r1[d] = load_atom16<NT>(base + (size_t)(kb0 + D + d) * 2048 + 256);
+          for (int d = 0; d < D; ++d) {
+            mma(r0[d], r1[d], kb0 + d);
+            r0[d] = load_atom16<NT>(base + (size_t)(kb0 + D + d) * 2048);
+            r1[d] = load_atom16<NT>(base + (size_t)(kb0 + D + d) * 2048 + 256);
+          }
+#pragma unroll
+          for (int d = 0; d < D; ++d) {
+            __builtin_amdgcn_sched_group_barrier(kSgDsRead, 1, 0);
+            __builtin_amdgcn_sched_group_barrier(kSgMfma, 2, 0);
+            __builtin_amdgcn_sched_group_barrier(kSgVmemRead, 2, 0);
+          }
         }
+        // last D k-blocks of the row: refill from the next row, else from the
+        // next chunk's first row, else not at all
+        const bool more_row = (uint32_t)w + 1 < nw;
+        if (more_row || ib_next < n_ib) {
+          const uint8_t *nb = more_row ? row_ptr(w + 1, ib0) : row_ptr(0, ib_next);
 #pragma unroll
-        for (int d = 0; d < D; ++d) {
-          __builtin_amdgcn_sched_group_barrier(kSgDsRead, 1, 0);
-          __builtin_amdgcn_sched_group_barrier(kSgMfma, 2, 0);
-          __builtin_amdgcn_sched_group_barrier(kSgVmemRead, 2, 0);
+          for (int d = 0; d < D; ++d) {
+            mma(r0[d], r1[d], kb0 + d);
+            r0[d] = load_atom16<NT>(nb + (size_t)d * 2048);
+            r1[d] = load_atom16<NT>(nb + (size_t)d * 2048 + 256);
+          }
+#pragma unroll
+          for (int d = 0; d < D; ++d) {
+            __builtin_amdgcn_sched_group_barrier(kSgDsRead, 1, 0);
+            __builtin_amdgcn_sched_group_barrier(kSgMfma, 2, 0);
+            __builtin_amdgcn_sched_group_barrier(kSgVmemRead, 2, 0);
+          }
+        } else {
+#pragma unroll
+          for (int d = 0; d < D; ++d) mma(r0[d], r1[d], kb0 + d);
         }
-      }
-      // last D k-blocks of the row: refill from the next row, else from the
-      // next chunk's first row, else not at all
-      const bool more_row = (uint32_t)w + 1 < nw;
-      if (more_row || ib_next < n_ib) {
-        const uint8_t *nb = more_row ? row_ptr(w + 1, ib0) : row_ptr(0, ib_next);
-#pragma unroll
-        for (int d = 0; d < D; ++d) {
-          mma(r0[d], r1[d], kb0 + d);
-          r0[d] = load_atom16<NT>(nb + (size_t)d * 2048);
-          r1[d] = load_atom16<NT>(nb + (size_t)d * 2048 + 256);
-        }
-#pragma unroll
-        for (int d = 0; d < D; ++d) {
-          __builtin_amdgcn_sched_group_barrier(kSgDsRead, 1, 0);
-          __builtin_amdgcn_sched_group_barrier(kSgMfma, 2, 0);
-          __builtin_amdgcn_sched_group_barrier(kSgVmemRead, 2, 0);
-        }
-      } else {
-#pragma unroll
-        for (int d = 0; d < D; ++d) mma(r0[d], r1[d], kb0 + d);
-      }
       }
     }
   }
