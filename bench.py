@@ -447,6 +447,8 @@ def main() -> int:
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--latency-steps", type=int, default=50)
     ap.add_argument("--no-tune", action="store_true", help="use the default scan variant")
+    ap.add_argument("--switch-bits", type=int, default=0,
+                    help="drain the answers with modulus switching to 2^bits (0: plain INTT)")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="only run a plain 1 GiB device copy (for HBM counter scaling)")
     args = ap.parse_args()
@@ -491,8 +493,9 @@ def main() -> int:
     qc = torch.empty((B, R, 2, K, N), dtype=torch.int32, device=dev)
     for b in range(B):
         qc[b] = torch.from_numpy(synth.uniform_query(args.seed, b, R, primes, N).view(np.int32)).to(dev)
-    ans = torch.empty((B, C, 2, K, N), dtype=torch.int32, device=dev)
-    jobs = [(db, B, qc, ans)]
+    sb = args.switch_bits
+    ans = torch.empty((B, C, 2, N) if sb else (B, C, 2, K, N), dtype=torch.int32, device=dev)
+    jobs = [(db, B, qc, ans, sb)]
     tune_report = None
     if not args.no_tune:
         tune_report = ctx.tune(db, B)
@@ -552,9 +555,11 @@ def main() -> int:
             "workload": (f"{'batch-1' if B == 1 else 'batched'} scan: N={N}, {K} primes < 2^28, "
                          f"p=2^8, DB R={R} x C={C} ({raw_bytes / 2**20:.0f} MiB raw, "
                          f"{db.device_bytes / 2**30:.2f} GiB NTT form), B={B} uniform "
-                         f"ciphertext-shaped queries"),
+                         f"ciphertext-shaped queries"
+                         + (f", answers switched to 2^{sb}" if sb else "")),
             "N": N, "primes": primes, "R": R, "C": C, "B": B,
             "raw_db_bytes": raw_bytes, "ntt_db_bytes": db.device_bytes,
+            "answer_switch_bits": sb,
             "db_load_s": round(load_s, 3),
         },
         "queries_per_s": round(B * args.steps / wall, 3),

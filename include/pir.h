@@ -184,12 +184,17 @@ pir_status pir_db_mul(pir_ctx *ctx, const pir_db *db, const uint32_t *query_ntt,
  * its queries, the scan, inverse NTT of its answers -- coefficient form in and
  * out.  Jobs may name different databases (different N, R, C); the scans of
  * all jobs run in one launch.  query_coeff: device [B][R][2][K][N] (left
- * unchanged); answer_coeff: device [B][C][2][K][N]. */
+ * unchanged).  switch_bits = 0: answer_coeff is device [B][C][2][K][N]
+ * (coefficient form).  switch_bits in [1, 32]: the drain is the fused inverse
+ * NTT and modulus switch of pir_intt_modswitch, and answer_coeff is device
+ * [B][C][2][N] words mod 2^switch_bits (K <= 2, else UNSUPPORTED); the NTT-form
+ * answers then take B*C*2*K*N*4 bytes of context workspace. */
 typedef struct {
   const pir_db *db;
   uint32_t B;
   const uint32_t *query_coeff;
   uint32_t *answer_coeff;
+  uint32_t switch_bits;
 } pir_job;
 
 pir_status pir_answer_batch(pir_ctx *ctx, const pir_job *jobs, size_t n_jobs,

@@ -351,12 +351,13 @@ ScanCfg group_cfg(const pir_ctx *ctx, const std::vector<ScanJob> &g) {
 
 // Workspace layout and scan jobs of a job list (see pir_answer_batch).
 struct BatchPlan {
-  size_t shared_q = 0, own_q = 0, atoms = 0, slot_major = 0;
+  size_t shared_q = 0, own_q = 0, atoms = 0, slot_major = 0, switched = 0;
   std::vector<ScanJob> b1, mf;      // fused groups: batch-1 kernel, batched kernel
   std::vector<uint32_t *> qntt;     // per job: where its NTT-form query goes
   std::vector<uint8_t *> qatoms;    // per job: its query atoms (batched kernel)
   std::vector<uint32_t *> sm;       // per job: its slot-major answers (batched kernel)
-  size_t bytes() const { return shared_q + own_q + atoms + slot_major; }
+  std::vector<uint32_t *> ans;      // per job: NTT-form answers before a modulus switch
+  size_t bytes() const { return shared_q + own_q + atoms + slot_major + switched; }
 };
 
 size_t al256(size_t x) { return (x + 255) & ~(size_t)255; }
@@ -371,6 +372,11 @@ pir_status plan_batch(pir_ctx *ctx, const pir_job *jobs, size_t n_jobs, BatchPla
     if (j.B < 1 || j.B > PIR_MAX_BATCH)
       return fail(ctx, PIR_ERR_INVALID_ARG, "job %zu: B=%u out of range", n, j.B);
     const DbDesc &d = j.db->desc;
+    if (j.switch_bits > 32)
+      return fail(ctx, PIR_ERR_INVALID_ARG, "job %zu: switch_bits=%u > 32", n, j.switch_bits);
+    if (j.switch_bits && d.K > 2)
+      return fail(ctx, PIR_ERR_UNSUPPORTED, "job %zu: modulus switching takes 1 or 2 primes", n);
+    if (j.switch_bits) p.switched += al256((size_t)j.B * d.C * 2 * d.K * d.N * 4);
     const size_t qb = al256((size_t)j.B * d.R * 2 * d.K * d.N * 4);
     if (j.B == 1) p.own_q += qb;
     else p.shared_q = std::max(p.shared_q, qb);
@@ -385,9 +391,11 @@ void place_batch(const pir_job *jobs, size_t n_jobs, uint8_t *base, BatchPlan &p
   uint8_t *own = base + p.shared_q;
   uint8_t *atoms = own + p.own_q;
   uint8_t *sm = atoms + p.atoms;
+  uint8_t *sw = sm + p.slot_major;
   p.qntt.assign(n_jobs, nullptr);
   p.qatoms.assign(n_jobs, nullptr);
   p.sm.assign(n_jobs, nullptr);
+  p.ans.assign(n_jobs, nullptr);
   p.b1.clear();
   p.mf.clear();
   for (size_t n = 0; n < n_jobs; ++n) {
@@ -404,7 +412,14 @@ void place_batch(const pir_job *jobs, size_t n_jobs, uint8_t *base, BatchPlan &p
       p.sm[n] = (uint32_t *)sm;
       sm += al256(answer_bytes(d, j.B));
     }
-    const ScanJob sj{d, p.qatoms[n], p.qntt[n], j.B == 1 ? j.answer_coeff : p.sm[n], j.B, 0,
+    // NTT-form answers: in place in answer_coeff, or in the workspace when the
+    // drain switches them into answer_coeff
+    p.ans[n] = j.answer_coeff;
+    if (j.switch_bits) {
+      p.ans[n] = (uint32_t *)sw;
+      sw += al256((size_t)j.B * d.C * 2 * d.K * d.N * 4);
+    }
+    const ScanJob sj{d, p.qatoms[n], p.qntt[n], j.B == 1 ? p.ans[n] : p.sm[n], j.B, 0,
                      d.K * d.N, 0, 0};
     (j.B == 1 ? p.b1 : p.mf).push_back(sj);
   }
@@ -726,11 +741,18 @@ pir_status enqueue_batch(pir_ctx *ctx, const pir_job *jobs, size_t n_jobs, uint8
     if (p.sm[n]) {
       StageTimer tm(ctx, s, PIR_STAGE_UNPACK);
       const uint32_t P = 2 * jobs[n].B * d.C;
-      HIP_OR_FAIL(ctx, launch_unpack_answers(p.sm[n], P, 0, P, d.K * d.N, jobs[n].answer_coeff, s));
+      HIP_OR_FAIL(ctx, launch_unpack_answers(p.sm[n], P, 0, P, d.K * d.N, p.ans[n], s));
     }
     StageTimer tm(ctx, s, PIR_STAGE_INTT);
-    HIP_OR_FAIL(ctx, launch_ntt(jobs[n].answer_coeff, (size_t)jobs[n].B * d.C * 2 * d.K, d.K,
-                                d.log2n, d.primes, true, s));
+    if (jobs[n].switch_bits) {
+      HIP_OR_FAIL(ctx, launch_intt_switch(p.ans[n], jobs[n].answer_coeff,
+                                          (size_t)jobs[n].B * d.C * 2, d.K,
+                                          jobs[n].db->params.primes, d.log2n, d.primes,
+                                          jobs[n].switch_bits, s));
+    } else {
+      HIP_OR_FAIL(ctx, launch_ntt(jobs[n].answer_coeff, (size_t)jobs[n].B * d.C * 2 * d.K, d.K,
+                                  d.log2n, d.primes, true, s));
+    }
   }
   return PIR_OK;
 }

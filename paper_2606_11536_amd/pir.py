@@ -38,7 +38,7 @@ class CParams(ct.Structure):
 
 class CJob(ct.Structure):
     _fields_ = [("db", ct.c_void_p), ("B", ct.c_uint32), ("query_coeff", ct.c_void_p),
-                ("answer_coeff", ct.c_void_p)]
+                ("answer_coeff", ct.c_void_p), ("switch_bits", ct.c_uint32)]
 
 
 SIGNATURES = {
@@ -286,12 +286,15 @@ class Context:
     @staticmethod
     def _jobs(jobs):
         arr = (CJob * len(jobs))()
-        for n, (db, B, qc, ac) in enumerate(jobs):
-            arr[n] = CJob(db.handle, B, qc.data_ptr(), ac.data_ptr())
+        for n, job in enumerate(jobs):
+            db, B, qc, ac = job[:4]
+            bits = job[4] if len(job) > 4 else 0
+            arr[n] = CJob(db.handle, B, qc.data_ptr(), ac.data_ptr(), bits)
         return arr
 
     def answer_batch(self, jobs, stream=None) -> None:
-        """Fused batch: jobs = [(db, B, query_coeff, answer_coeff), ...] (coefficient form)."""
+        """Fused batch: jobs = [(db, B, query_coeff, answer_coeff[, switch_bits]), ...]
+        (coefficient form; with switch_bits the answers are [B][C][2][N] mod 2^bits)."""
         _check(lib.pir_answer_batch(self.handle, self._jobs(jobs), len(jobs), _stream(stream)),
                self.handle)
 

@@ -101,3 +101,61 @@ def test_arguments(ctx):
     q3 = op.ntt_primes(rg.N, 3)
     with pytest.raises(pir.PirError):
         ctx.intt_modswitch(pir.Params(10, q3, 8), src, out, 29, n_polys=1)
+
+
+JOBS = [(11, 2, 40, 20, 1, 29), (11, 2, 40, 20, 3, 29), (10, 1, 33, 9, 2, 0),
+        (11, 2, 64, 17, 5, 24), (10, 2, 70, 12, 1, 0)]
+
+
+def _batch(ctx, seed):
+    rng = np.random.default_rng(seed)
+    jobs, checks = [], []
+    for n, (log2n, K, R, C, B, bits) in enumerate(JOBS):
+        rg = ring(log2n, K)
+        raw = synth.db_bytes(seed + n, R, C, rg.N)
+        db = ctx.load_db(rg.pir_params(), raw, R, C)
+        qc = residues(rng, (B, R, 2), rg)
+        out = empty_dev((B, C, 2, rg.N) if bits else (B, C, 2, K, rg.N))
+        jobs.append((db, B, to_dev(qc), out, bits))
+        y = osc.db_mul(osc.db_ntt(raw, rg.primes, rg.psis), osc.query_ntt(qc, rg.primes, rg.psis),
+                       rg.primes)
+        checks.append(oms.intt_switch(y, rg.primes, rg.psis, bits) if bits
+                      else osc.answer_intt(y, rg.primes, rg.psis))
+    return jobs, checks
+
+
+def test_answer_batch_with_switching(ctx):
+    """Batch-1 and batched jobs, with and without a modulus switch, in one call:
+    switched answers are [B][C][2][N] words equal to the oracle's switch of the
+    oracle's answers; the others are unchanged coefficient-form answers."""
+    from paper_2606_11536_amd import pir
+    jobs, checks = _batch(ctx, 300)
+    ctx.answer_batch(jobs)
+    for (db, B, qd, out, bits), exp in zip(jobs, checks):
+        assert np.array_equal(to_host(out), exp), (B, bits)
+    bad = [(jobs[0][0], 1, jobs[0][2], jobs[0][3], 33)]
+    with pytest.raises(pir.PirError):
+        ctx.answer_batch(bad)
+    for j in jobs:
+        j[0].free()
+
+
+def test_plan_replays_with_switching(ctx):
+    """The same job list captured in a HIP graph: three replays, with eager work
+    and synchronisation between them, each equal to the oracle."""
+    import torch
+    jobs, checks = _batch(ctx, 400)
+    pl = ctx.plan(jobs)
+    scratch = torch.zeros(1 << 20, dtype=torch.int32, device="cuda")
+    for r in range(3):
+        for j in jobs:
+            j[3].zero_()
+        pl.launch()
+        torch.cuda.synchronize()
+        for (db, B, qd, out, bits), exp in zip(jobs, checks):
+            assert np.array_equal(to_host(out), exp), (r, B, bits)
+        scratch.add_(1)
+        torch.cuda.synchronize()
+    pl.close()
+    for j in jobs:
+        j[0].free()
