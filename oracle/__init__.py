@@ -19,6 +19,8 @@ Modules
             Sec. 4 INT32 modular GEMM), and a Freivalds full-output check.
 ``modswitch`` modulus switching of answers from Q down to 2^t (Sec. 4.3,
             App. D.5) and decryption at the reduced modulus.
+``scalar``  the scalar-HE database GEMM mod 2^32 (Sec. 4.1) and a toy
+            SimplePIR round trip (Sec. 2).
 
 All arithmetic is on exact integers (Python ints, or numpy uint64/int64 with
 every intermediate bounded below 2**63); nothing is approximated.
