@@ -168,6 +168,30 @@ pir_status pir_intt(pir_ctx *ctx, const pir_params *params, uint32_t *polys, siz
 pir_status pir_intt_modswitch(pir_ctx *ctx, const pir_params *params, const uint32_t *answer_ntt,
                               size_t n_polys, uint32_t bits, uint32_t *out, pir_stream stream);
 
+/* ---- scalar-HE database GEMM mod 2^32 (Sec. 4.1: an INT8 database times
+ * INT32 query words on the matrix engines, four byte-wise products shifted
+ * and added mod 2^32; Sec. 2: the online step of SimplePIR with multi-client
+ * batching).  pir_sdb_load copies an int8 database db[D1][D0] (row-major,
+ * host or device memory per db_is_device; the caller may free it once the
+ * call returns) into device tiles of ceil(D1/32)*32 x D0_pad bytes, D0_pad =
+ * D0 rounded up to 256 (1 byte per entry).  1 <= D1 <= PIR_SDB_MAX_D1,
+ * 1 <= D0 <= PIR_SDB_MAX_D0 (every int32 partial sum of the product is then
+ * exact).  Errors: INVALID_ARG, OUT_OF_MEMORY, BUDGET, DEVICE.
+ * pir_sdb_mul: query device uint32 [B][D0], out device uint32 [B][D1],
+ *   out[b][r] = sum_c db[r][c] * query[b][c]  (mod 2^32),
+ * 1 <= B <= PIR_MAX_BATCH; uses 32 KiB x ceil(D0/256) x ceil(B/32) of
+ * context workspace for the split queries.  Asynchronous on `stream`; timed as the
+ * pack and scan stages when profiling is on.  pir_sdb_free waits for the
+ * device and releases the tiles. */
+#define PIR_SDB_MAX_D0 131071u
+#define PIR_SDB_MAX_D1 (1u << 26)
+typedef struct pir_sdb pir_sdb;
+pir_status pir_sdb_load(pir_ctx *ctx, const int8_t *db, int db_is_device, uint32_t D1,
+                        uint32_t D0, pir_stream stream, pir_sdb **out);
+pir_status pir_sdb_mul(pir_ctx *ctx, const pir_sdb *db, const uint32_t *query, uint32_t B,
+                       uint32_t *out, pir_stream stream);
+void pir_sdb_free(pir_sdb *db);
+
 /* ---- the scan in NTT form (Sec. 3.2 step 6; Sec. 4 INT32 modular GEMM).
  * query_ntt: device [B][R][2][K][N], NTT form; answer_ntt: device
  * [B][C][2][K][N], NTT form, fully overwritten:

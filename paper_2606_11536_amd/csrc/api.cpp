@@ -652,6 +652,89 @@ pir_status pir_intt(pir_ctx *ctx, const pir_params *params, uint32_t *polys, siz
   return ntt_common(ctx, params, polys, n_polys, stream, true);
 }
 
+pir_status pir_sdb_load(pir_ctx *ctx, const int8_t *db, int db_is_device, uint32_t D1,
+                        uint32_t D0, pir_stream stream, pir_sdb **out) {
+  if (!ctx || !out) return PIR_ERR_INVALID_ARG;
+  *out = nullptr;
+  if (!db) return fail(ctx, PIR_ERR_INVALID_ARG, "db is NULL");
+  if (D1 < 1 || D1 > PIR_SDB_MAX_D1 || D0 < 1 || D0 > PIR_SDB_MAX_D0)
+    return fail(ctx, PIR_ERR_INVALID_ARG, "D1=%u or D0=%u out of range", D1, D0);
+  DeviceGuard g(ctx->device);
+  hipStream_t s = (hipStream_t)stream;
+  const uint32_t n_rb = (D1 + 31) / 32, n_kb = ((D0 + 31) / 32 + 7) / 8 * 8;
+  const size_t bytes = (size_t)n_rb * n_kb * kAtomBytes;
+  pir_sdb *h = new (std::nothrow) pir_sdb;
+  if (!h) return fail(ctx, PIR_ERR_OUT_OF_MEMORY, "host allocation failed");
+  void *atoms = nullptr;
+  pir_status st = dev_alloc(ctx, &atoms, bytes, "scalar database");
+  if (st != PIR_OK) {
+    delete h;
+    return st;
+  }
+  const int8_t *src = db;
+  void *staging = nullptr;
+  const size_t raw = (size_t)D1 * D0;
+  auto bail = [&](pir_status code) {
+    dev_free(ctx, staging, raw);
+    dev_free(ctx, atoms, bytes);
+    delete h;
+    return code;
+  };
+  if (!db_is_device) {
+    if ((st = dev_alloc(ctx, &staging, raw, "scalar database staging")) != PIR_OK) return bail(st);
+    if (hipMemcpyAsync(staging, db, raw, hipMemcpyHostToDevice, s) != hipSuccess)
+      return bail(fail(ctx, PIR_ERR_DEVICE, "host copy failed"));
+    src = (const int8_t *)staging;
+  }
+  if (launch_sdb_pack(src, (uint8_t *)atoms, D1, D0, n_rb, n_kb, s) != hipSuccess)
+    return bail(fail(ctx, PIR_ERR_DEVICE, "database pack failed"));
+  if (staging) {
+    if (hipStreamSynchronize(s) != hipSuccess)
+      return bail(fail(ctx, PIR_ERR_DEVICE, "stream synchronisation failed"));
+    dev_free(ctx, staging, raw);
+    staging = nullptr;
+  }
+  h->ctx = ctx;
+  h->D1 = D1;
+  h->D0 = D0;
+  h->n_rb = n_rb;
+  h->n_kb = n_kb;
+  h->bytes = bytes;
+  h->atoms = (uint8_t *)atoms;
+  *out = h;
+  return PIR_OK;
+}
+
+pir_status pir_sdb_mul(pir_ctx *ctx, const pir_sdb *db, const uint32_t *query, uint32_t B,
+                       uint32_t *out, pir_stream stream) {
+  if (!ctx) return PIR_ERR_INVALID_ARG;
+  if (!db || !query || !out) return fail(ctx, PIR_ERR_INVALID_ARG, "null argument");
+  if (db->ctx != ctx) return fail(ctx, PIR_ERR_INVALID_ARG, "database belongs to another context");
+  if (B < 1 || B > PIR_MAX_BATCH) return fail(ctx, PIR_ERR_INVALID_ARG, "B=%u out of range", B);
+  DeviceGuard g(ctx->device);
+  const uint32_t n_cb = ((B + 7) / 8 + 3) / 4 * 4;
+  pir_status st = ensure_ws(ctx, (size_t)db->n_kb * n_cb * kAtomBytes);
+  if (st != PIR_OK) return st;
+  hipStream_t s = (hipStream_t)stream;
+  uint8_t *qa = (uint8_t *)ctx->ws;
+  {
+    StageTimer tm(ctx, s, PIR_STAGE_PACK);
+    HIP_OR_FAIL(ctx, launch_sq_pack(query, qa, B, db->D0, db->n_kb, n_cb, s));
+  }
+  StageTimer tm(ctx, s, PIR_STAGE_SCAN, true);
+  HIP_OR_FAIL(ctx, launch_sgemm(db->atoms, qa, out, db->D1, B, db->n_rb, db->n_kb, n_cb, s,
+                                tm.start(), tm.stop()));
+  return PIR_OK;
+}
+
+void pir_sdb_free(pir_sdb *db) {
+  if (!db) return;
+  DeviceGuard g(db->ctx->device);
+  (void)hipDeviceSynchronize();
+  dev_free(db->ctx, db->atoms, db->bytes);
+  delete db;
+}
+
 pir_status pir_intt_modswitch(pir_ctx *ctx, const pir_params *params, const uint32_t *answer_ntt,
                               size_t n_polys, uint32_t bits, uint32_t *out, pir_stream stream) {
   if (!ctx) return PIR_ERR_INVALID_ARG;

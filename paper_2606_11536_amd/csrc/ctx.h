@@ -36,6 +36,14 @@ struct pir_ctx {
   std::map<std::vector<uint32_t>, pir::ScanCfg> batch_cfg;
 };
 
+// A scalar-HE database: D1 x D0 int8 entries in GEMM atoms.
+struct pir_sdb {
+  pir_ctx *ctx = nullptr;
+  uint32_t D1 = 0, D0 = 0, n_rb = 0, n_kb = 0;
+  size_t bytes = 0;
+  uint8_t *atoms = nullptr;
+};
+
 struct pir_db {
   pir_ctx *ctx = nullptr;
   pir_params params{};

@@ -78,6 +78,16 @@ hipError_t launch_ntt(uint32_t *data, size_t n_rows, uint32_t K, uint32_t log2n,
 hipError_t launch_intt_switch(const uint32_t *src, uint32_t *dst, size_t n_polys, uint32_t K,
                               const uint32_t *q, uint32_t log2n, const DevPrime *primes,
                               uint32_t bits, hipStream_t s);
+// Scalar-HE database GEMM mod 2^32 (sgemm.hip): database int8 [D1][D0] into
+// atoms [n_rb][n_kb]; queries uint32 [B][D0] into digit atoms [n_kb][n_cb];
+// out [B][D1] = DB Q^T mod 2^32.  n_kb a multiple of 8, n_cb of 4.
+hipError_t launch_sdb_pack(const int8_t *db, uint8_t *atoms, uint32_t D1, uint32_t D0,
+                           uint32_t n_rb, uint32_t n_kb, hipStream_t s);
+hipError_t launch_sq_pack(const uint32_t *q, uint8_t *atoms, uint32_t B, uint32_t D0,
+                          uint32_t n_kb, uint32_t n_cb, hipStream_t s);
+hipError_t launch_sgemm(const uint8_t *db, const uint8_t *q, uint32_t *out, uint32_t D1,
+                        uint32_t B, uint32_t n_rb, uint32_t n_kb, uint32_t n_cb, hipStream_t s,
+                        hipEvent_t e0 = nullptr, hipEvent_t e1 = nullptr);
 hipError_t launch_ntt_copy(const uint32_t *src, uint32_t *dst, size_t n_rows, uint32_t K,
                            uint32_t log2n, const DevPrime *primes, hipStream_t s);
 // Lift + forward NTT of a slab of raw database rows: raw [S][C][N] uint8 ->

@@ -60,6 +60,9 @@ SIGNATURES = {
     "pir_ntt": (ct.c_int, [_P, ct.POINTER(CParams), _P, ct.c_size_t, _P]),
     "pir_intt": (ct.c_int, [_P, ct.POINTER(CParams), _P, ct.c_size_t, _P]),
     "pir_intt_modswitch": (ct.c_int, [_P, ct.POINTER(CParams), _P, ct.c_size_t, _U32, _P, _P]),
+    "pir_sdb_load": (ct.c_int, [_P, _P, ct.c_int, _U32, _U32, _P, ct.POINTER(ct.c_void_p)]),
+    "pir_sdb_mul": (ct.c_int, [_P, _P, _P, _U32, _P, _P]),
+    "pir_sdb_free": (None, [_P]),
     "pir_db_mul": (ct.c_int, [_P, _P, _P, _U32, _P, _P]),
     "pir_answer_batch": (ct.c_int, [_P, ct.POINTER(CJob), ct.c_size_t, _P]),
     "pir_scan_variants": (ct.c_uint32, [_U32]),
@@ -166,6 +169,18 @@ def _ptr(t) -> ct.c_void_p:
     return ct.c_void_p(t.data_ptr())
 
 
+class ScalarDatabase:
+    """A device-resident int8 D1 x D0 database for the scalar-HE GEMM, owned by libpir."""
+
+    def __init__(self, ctx: "Context", handle: ct.c_void_p, D1: int, D0: int):
+        self.ctx, self.handle, self.D1, self.D0 = ctx, handle, D1, D0
+
+    def free(self) -> None:
+        if self.handle and self.ctx.handle:
+            lib.pir_sdb_free(self.handle)
+        self.handle = None
+
+
 class Database:
     """A device-resident NTT-form database owned by libpir."""
 
@@ -257,6 +272,28 @@ class Context:
         db = Database(self, h, params, R, C)
         self._dbs.add(db)
         return db
+
+    def load_sdb(self, db, D1: int, D0: int, stream=None) -> ScalarDatabase:
+        """Tile an int8 [D1][D0] database (numpy array or torch tensor) for pir_sdb_mul."""
+        h = ct.c_void_p()
+        if hasattr(db, "data_ptr"):
+            assert db.is_contiguous() and db.numel() == D1 * D0 and db.element_size() == 1
+            is_dev, ptr = int(db.is_cuda), ct.c_void_p(db.data_ptr())
+        else:
+            import numpy as np
+            db = np.ascontiguousarray(db, dtype=np.int8)
+            assert db.size == D1 * D0
+            is_dev, ptr = 0, db.ctypes.data_as(ct.c_void_p)
+        _check(lib.pir_sdb_load(self.handle, ptr, is_dev, D1, D0, _stream(stream), ct.byref(h)),
+               self.handle)
+        sdb = ScalarDatabase(self, h, D1, D0)
+        self._dbs.add(sdb)
+        return sdb
+
+    def sdb_mul(self, db: ScalarDatabase, query, B: int, out, stream=None) -> None:
+        """out [B][D1] = query [B][D0] x db^T mod 2^32 (uint32 device tensors as int32)."""
+        _check(lib.pir_sdb_mul(self.handle, db.handle, _ptr(query), B, _ptr(out), _stream(stream)),
+               self.handle)
 
     def ntt(self, params: Params, polys, n_polys: int | None = None, stream=None) -> None:
         """In-place forward NTT of [n_polys][K][N] residues (device tensor)."""
