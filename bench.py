@@ -48,6 +48,9 @@ SERVE = dict(log2n=11, K=2, R=4096, C=2048, max_batch=128, n_chunks=64, pool=16,
 # answer drain with modulus switching: the answers of one batch of 32 queries over
 # 1024 columns (32 x 1024 x 2 polynomials), switched to 2^29
 DRAIN = dict(log2n=11, K=2, polys=32 * 1024 * 2, bits=29)
+# scalar-HE database GEMM mod 2^32: D1 x D0 int8 database (16 GiB, the paper's
+# D0 = 65536 words per query), one query and a batch of 32
+SCALAR = dict(D1=1 << 18, D0=1 << 16, batches=[1, 32])
 # three databases of uneven shape in one batch: (log2n, K, R, C)
 MULTIDB = [(12, 2, 1024, 512), (11, 2, 3000, 700), (11, 2, 256, 4096)]
 
@@ -376,6 +379,85 @@ def drain(args) -> dict:
     return res
 
 
+def scalar(args) -> dict:
+    """pir_sdb_mul over a 16 GiB int8 database for one query and for a batch of 32."""
+    import torch
+
+    from paper_2606_11536_amd import pir
+    D1, D0 = SCALAR["D1"], SCALAR["D0"]
+    cpu = None
+    if not args.no_cpu_baseline:
+        from oracle import scalar as oscl
+        rng = np.random.default_rng(args.seed)
+        rows = 4096
+        dbs = rng.integers(-128, 128, (rows, D0), dtype=np.int64).astype(np.int8)
+        qs = rng.integers(0, 1 << 32, (1, D0), dtype=np.uint64).astype(np.uint32)
+        t = time.perf_counter()
+        reps = 0
+        while time.perf_counter() - t < 2.0:
+            oscl.db_gemm(dbs, qs)
+            reps += 1
+        sec = (time.perf_counter() - t) / reps
+        cpu = {"value": round(rows * D0 / sec / 1e9, 4), "unit": "GB/s", "cores": 1,
+               "kind": "oracle", "sample": f"oracle GEMM of one query over {rows} rows x {D0} "
+                                           f"(int64 numpy product), {reps} runs in 2 s"}
+    ctx = pir.Context(0)
+    gen = torch.Generator(device="cuda").manual_seed(args.seed)
+    raw = torch.randint(-128, 128, (D1, D0), generator=gen, device="cuda", dtype=torch.int8)
+    t = time.perf_counter()
+    sdb = ctx.load_sdb(raw, D1, D0)
+    torch.cuda.synchronize()
+    load_s = time.perf_counter() - t
+    del raw
+    torch.cuda.empty_cache()
+    runs = []
+    for B in SCALAR["batches"]:
+        q = torch.randint(-(1 << 31), 1 << 31, (B, D0), generator=gen, device="cuda",
+                          dtype=torch.int64).to(torch.int32)
+        out = torch.empty((B, D1), dtype=torch.int32, device="cuda")
+        for _ in range(args.warmup):
+            ctx.sdb_mul(sdb, q, B, out)
+        torch.cuda.synchronize()
+        ctx.profile(True, stages=("scan",))
+        t0 = time.perf_counter()
+        for _ in range(args.steps):
+            ctx.sdb_mul(sdb, q, B, out)
+        torch.cuda.synchronize()
+        wall = time.perf_counter() - t0
+        ms, n = ctx.profile_read("scan")
+        ctx.profile(False)
+        k_ms = ms / max(n, 1)
+        alg = D1 * D0 + B * D0 * 4 + B * D1 * 4
+        ops = 2 * D1 * D0 * B * 4                     # int8 MACs of the four digit GEMMs, x2
+        runs.append({"B": B, "ms_per_step": round(wall * 1e3 / args.steps, 4),
+                     "db_GBps": round(D1 * D0 * B * args.steps / wall / 1e9, 2),
+                     "queries_per_s": round(B * args.steps / wall, 2),
+                     "kernel_ms": round(k_ms, 4),
+                     "hbm_frac": round(alg / (k_ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
+                     "int8_TOPS": round(ops / (k_ms * 1e-3) / 1e12, 1)})
+        log(f"[scalar] B={B}: {runs[-1]}")
+    one = runs[0]
+    res = {
+        "metric": "scalar-HE DB GEMM GB/s (int8 DB bytes x queries / s)",
+        "value": one["db_GBps"], "unit": "GB/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": one["ms_per_step"], "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "i8", "data": "synthetic",
+        "config": {"workload": f"scalar-HE database GEMM mod 2^32: {D1} x {D0} int8 "
+                               f"({D1 * D0 / 2**30:.0f} GiB), uniform uint32 query words",
+                   "D1": D1, "D0": D0, "db_load_s": round(load_s, 3)},
+        "batches": runs,
+        "roofline": {"bound": "hbm", "kernel": "k_sgemm", "achieved": round(
+            one["hbm_frac"] * HBM_PEAK_GBS, 2), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": one["hbm_frac"], "traffic": None,
+            "alg_bytes_per_launch": D1 * D0 + D0 * 4 + D1 * 4, "avg_launch_ms": one["kernel_ms"]},
+    }
+    if cpu is not None:
+        res["cpu_baseline"] = cpu
+    sdb.free()
+    ctx.close()
+    return res
+
+
 def multidb(args) -> dict:
     """Three uneven databases, 1..64 queries each, one fused batch, HIP-graph replays."""
     import torch
@@ -440,7 +522,7 @@ def main() -> int:
     ap.add_argument("--steps", type=int, default=50)
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--workload", default="batch1",
-                    choices=sorted(WORKLOADS) + ["serving", "multidb", "drain"])
+                    choices=sorted(WORKLOADS) + ["serving", "multidb", "drain", "scalar"])
     ap.add_argument("--serve-seconds", type=float, default=3.0)
     ap.add_argument("--serve-max-requests", type=int, default=1500)
     ap.add_argument("--seed", type=int, default=0)
@@ -458,8 +540,8 @@ def main() -> int:
     if args.calibrate_copy:
         calibrate_copy()
         return 0
-    if args.workload in ("serving", "multidb", "drain"):
-        fn = {"serving": serve, "multidb": multidb, "drain": drain}[args.workload]
+    if args.workload in ("serving", "multidb", "drain", "scalar"):
+        fn = {"serving": serve, "multidb": multidb, "drain": drain, "scalar": scalar}[args.workload]
         print(json.dumps(fn(args)), flush=True)
         return 0
 
