@@ -176,7 +176,8 @@ pir_status pir_intt_modswitch(pir_ctx *ctx, const pir_params *params, const uint
  * call returns) into device tiles of ceil(D1/32)*32 x D0_pad bytes, D0_pad =
  * D0 rounded up to 256 (1 byte per entry).  1 <= D1 <= PIR_SDB_MAX_D1,
  * 1 <= D0 <= PIR_SDB_MAX_D0 (every int32 partial sum of the product is then
- * exact).  Errors: INVALID_ARG, OUT_OF_MEMORY, BUDGET, DEVICE.
+ * exact), at most 2^40 bytes of tiles.  Errors: INVALID_ARG, OUT_OF_MEMORY,
+ * BUDGET, DEVICE.
  * pir_sdb_mul: query device uint32 [B][D0], out device uint32 [B][D1],
  *   out[b][r] = sum_c db[r][c] * query[b][c]  (mod 2^32),
  * 1 <= B <= PIR_MAX_BATCH; uses 32 KiB x ceil(D0/256) x ceil(B/32) of

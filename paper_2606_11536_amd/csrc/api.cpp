@@ -662,6 +662,8 @@ pir_status pir_sdb_load(pir_ctx *ctx, const int8_t *db, int db_is_device, uint32
   DeviceGuard g(ctx->device);
   hipStream_t s = (hipStream_t)stream;
   const uint32_t n_rb = (D1 + 31) / 32, n_kb = ((D0 + 31) / 32 + 7) / 8 * 8;
+  if ((size_t)n_rb * n_kb > ((size_t)1 << 30))  // atom indices stay 32-bit
+    return fail(ctx, PIR_ERR_INVALID_ARG, "D1=%u x D0=%u is more than 2^40 bytes of tiles", D1, D0);
   const size_t bytes = (size_t)n_rb * n_kb * kAtomBytes;
   pir_sdb *h = new (std::nothrow) pir_sdb;
   if (!h) return fail(ctx, PIR_ERR_OUT_OF_MEMORY, "host allocation failed");
