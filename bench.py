@@ -50,7 +50,7 @@ SERVE = dict(log2n=11, K=2, R=4096, C=2048, max_batch=128, n_chunks=64, pool=16,
 DRAIN = dict(log2n=11, K=2, polys=32 * 1024 * 2, bits=29)
 # scalar-HE database GEMM mod 2^32: D1 x D0 int8 database (16 GiB, the paper's
 # D0 = 65536 words per query), one query and a batch of 32
-SCALAR = dict(D1=1 << 18, D0=1 << 16, batches=[1, 32])
+SCALAR = dict(D1=1 << 18, D0=1 << 16, batches=[1, 16, 32])
 # three databases of uneven shape in one batch: (log2n, K, R, C)
 MULTIDB = [(12, 2, 1024, 512), (11, 2, 3000, 700), (11, 2, 256, 4096)]
 

@@ -93,67 +93,94 @@ struct SgArgs {
 // Block = 4 waves; wave w of row group rg owns row blocks (4 rg + w) JBW ..
 // + JBW - 1 and the CBW column blocks of column tile ct.  The column tiles of
 // one row group are adjacent logical blocks, so they run together and read
-// the group's database atoms from HBM once.  Atoms come through a register
-// ring D k-blocks deep; the loads of the last D steps are clamped to the
-// last k-block (valid memory, never used).
-template <int JBW, int CBW, int D>
+// the group's database atoms from HBM once.  Database atoms come through a
+// register ring D k-blocks deep (the loads of the last D steps are clamped to
+// the last k-block: valid memory, never used).  Query atoms are shared
+// through LDS: per chunk of KC k-blocks the four waves load the chunk's
+// KC x CBW query atoms once (a quarter each, into registers), write them to
+// one of two LDS buffers and meet at a barrier; every wave then reads its B
+// operands from LDS.  The loads of chunk n + 1 go out at the start of chunk n
+// and are written at its end, into the buffer last read in chunk n - 1.
+template <int JBW, int CBW, int D, int KC>
 __global__ __launch_bounds__(256) void k_sgemm(const SgArgs a) {
+  static_assert(KC % D == 0 && (KC * CBW) % 4 == 0, "chunk shape");
+  constexpr int kPer = KC * CBW / 4;  // staged atoms per wave per chunk
+  __shared__ uint4 sq[2][KC * CBW * 64];
   const uint32_t L = xcd_logical(blockIdx.x, gridDim.x);
   if (L >= a.total) return;
   const uint32_t ct = L % a.n_ct, rg = L / a.n_ct;
   const uint32_t lane = threadIdx.x & 63, wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const uint32_t rb0 = (rg * 4 + wave) * JBW, cb0 = ct * CBW, nkb = a.n_kb;
   const v4i *pa[JBW];
-  const v4i *pb[CBW];
 #pragma unroll
   for (int w = 0; w < JBW; ++w) {
     const uint32_t rb = rb0 + w < a.n_rb ? rb0 + w : a.n_rb - 1;  // past the end: discarded
     pa[w] = reinterpret_cast<const v4i *>(a.db + (size_t)rb * nkb * kAtomBytes) + lane;
   }
+  const uint4 *qa = reinterpret_cast<const uint4 *>(a.q) + lane;
+  // staged atom i = wave + 4 r of a chunk is (kk, c) = (i / CBW, i % CBW)
+  auto stage_load = [&](uint32_t chunk, uint4 (&st)[kPer]) {
 #pragma unroll
-  for (int c = 0; c < CBW; ++c)
-    pb[c] = reinterpret_cast<const v4i *>(a.q + (size_t)(cb0 + c) * kAtomBytes) + lane;
-  const size_t qstride = (size_t)a.n_cb * 64;  // v4i per k-block of query atoms
+    for (int r = 0; r < kPer; ++r) {
+      const uint32_t i = wave + 4 * r, kb = chunk * KC + i / CBW;
+      const uint32_t kbc = kb < nkb ? kb : nkb - 1;  // past the end: never read
+      st[r] = qa[((size_t)kbc * a.n_cb + cb0 + i % CBW) * 64];
+    }
+  };
+  auto stage_store = [&](uint32_t buf, const uint4 (&st)[kPer]) {
+#pragma unroll
+    for (int r = 0; r < kPer; ++r) sq[buf][(wave + 4 * r) * 64 + lane] = st[r];
+  };
 
   v16i acc[JBW][CBW];
 #pragma unroll
   for (int w = 0; w < JBW; ++w)
 #pragma unroll
     for (int c = 0; c < CBW; ++c) acc[w][c] = v16i{};
-  v4i ra[D][JBW], rq[D][CBW];
+  v4i ra[D][JBW];
 #pragma unroll
-  for (int d = 0; d < D; ++d) {
+  for (int d = 0; d < D; ++d)
 #pragma unroll
     for (int w = 0; w < JBW; ++w) ra[d][w] = __builtin_nontemporal_load(pa[w] + (size_t)d * 64);
+  uint4 st[kPer];
+  stage_load(0, st);
+  stage_store(0, st);
+  __syncthreads();
+  const uint32_t nch = nkb / KC;
+  for (uint32_t ch = 0; ch < nch; ++ch) {
+    const uint32_t buf = ch & 1;
+    stage_load(ch + 1, st);
+    for (uint32_t kk0 = 0; kk0 < (uint32_t)KC; kk0 += D) {
 #pragma unroll
-    for (int c = 0; c < CBW; ++c) rq[d][c] = pb[c][(size_t)d * qstride];
-  }
-  for (uint32_t kb0 = 0; kb0 < nkb; kb0 += D) {
+      for (int d = 0; d < D; ++d) {
+        const uint32_t kb = ch * KC + kk0 + d;
+        v4i bq[CBW];
 #pragma unroll
-    for (int d = 0; d < D; ++d) {
+        for (int c = 0; c < CBW; ++c) {
+          const uint4 u = sq[buf][((kk0 + d) * CBW + c) * 64 + lane];
+          bq[c] = v4i{(int)u.x, (int)u.y, (int)u.z, (int)u.w};
+        }
 #pragma unroll
-      for (int w = 0; w < JBW; ++w)
+        for (int w = 0; w < JBW; ++w)
 #pragma unroll
-        for (int c = 0; c < CBW; ++c)
-          acc[w][c] = __builtin_amdgcn_mfma_i32_32x32x32_i8(ra[d][w], rq[d][c], acc[w][c], 0, 0, 0);
-      const uint32_t nk = kb0 + D + d < nkb ? kb0 + D + d : nkb - 1;
+          for (int c = 0; c < CBW; ++c)
+            acc[w][c] = __builtin_amdgcn_mfma_i32_32x32x32_i8(ra[d][w], bq[c], acc[w][c], 0, 0, 0);
+        const uint32_t nk = kb + D < nkb ? kb + D : nkb - 1;
 #pragma unroll
-      for (int w = 0; w < JBW; ++w) ra[d][w] = __builtin_nontemporal_load(pa[w] + (size_t)nk * 64);
-#pragma unroll
-      for (int c = 0; c < CBW; ++c) rq[d][c] = pb[c][(size_t)nk * qstride];
+        for (int w = 0; w < JBW; ++w) ra[d][w] = __builtin_nontemporal_load(pa[w] + (size_t)nk * 64);
+      }
     }
+    stage_store(buf ^ 1, st);
+    __syncthreads();
   }
 
-  // Epilogue: lane (4 b' + k) of a quad holds digit k's sums; shift by 8 k,
-  // add over the quad (every lane then holds the full sum), and lane k stores
-  // the rows whose register index is k mod 4.
-  const uint32_t k = lane & 3, bq = (lane >> 2) & 7, hi = lane >> 5;
+  const uint32_t k = lane & 3, bq8 = (lane >> 2) & 7, hi = lane >> 5;
 #pragma unroll
   for (int w = 0; w < JBW; ++w) {
     const uint32_t rb = rb0 + w;
 #pragma unroll
     for (int c = 0; c < CBW; ++c) {
-      const uint32_t b = (cb0 + c) * 8 + bq;
+      const uint32_t b = (cb0 + c) * 8 + bq8;
 #pragma unroll
       for (int j = 0; j < 4; ++j) {
         uint32_t v[4];
@@ -172,10 +199,10 @@ __global__ __launch_bounds__(256) void k_sgemm(const SgArgs a) {
   }
 }
 
-template <int JBW, int CBW, int D>
-hipError_t run_sgemm(const uint8_t *db, const uint8_t *q, uint32_t *out, uint32_t D1, uint32_t B,
-                     uint32_t n_rb, uint32_t n_kb, uint32_t n_cb, hipStream_t s, hipEvent_t e0,
-                     hipEvent_t e1) {
+template <int JBW, int CBW, int D, int KC>
+hipError_t run_sgemm(const uint8_t *db, const uint8_t *q, uint32_t *out, uint32_t D1,
+                         uint32_t B, uint32_t n_rb, uint32_t n_kb, uint32_t n_cb, hipStream_t s,
+                         hipEvent_t e0, hipEvent_t e1) {
   SgArgs a{};
   a.db = db;
   a.q = q;
@@ -185,11 +212,11 @@ hipError_t run_sgemm(const uint8_t *db, const uint8_t *q, uint32_t *out, uint32_
   a.n_rb = n_rb;
   a.n_kb = n_kb;
   a.n_cb = n_cb;
-  a.n_ct = ((B + 7) / 8 + CBW - 1) / CBW;  // tiles holding queries; n_cb covers them
+  a.n_ct = ((B + 7) / 8 + CBW - 1) / CBW;
   a.n_rg = (n_rb + 4 * JBW - 1) / (4 * JBW);
   a.total = a.n_rg * a.n_ct;
   const uint32_t grid = (a.total + 7) / 8 * 8;
-  hipExtLaunchKernelGGL(k_sgemm<JBW, CBW, D>, dim3(grid), dim3(256), 0, s, e0, e1, 0, a);
+  hipExtLaunchKernelGGL(k_sgemm<JBW, CBW, D, KC>, dim3(grid), dim3(256), 0, s, e0, e1, 0, a);
   return hipGetLastError();
 }
 
@@ -217,9 +244,9 @@ hipError_t launch_sgemm(const uint8_t *db, const uint8_t *q, uint32_t *out, uint
   const uint32_t used = (B + 7) / 8;  // column blocks that hold queries
   if (n_kb % 8 != 0 || n_cb % 4 != 0 || n_rb == 0 || used == 0 || used > n_cb)
     return hipErrorInvalidValue;
-  if (used <= 1) return run_sgemm<2, 1, 8>(db, q, out, D1, B, n_rb, n_kb, n_cb, s, e0, e1);
-  if (used <= 2) return run_sgemm<2, 2, 8>(db, q, out, D1, B, n_rb, n_kb, n_cb, s, e0, e1);
-  return run_sgemm<2, 4, 8>(db, q, out, D1, B, n_rb, n_kb, n_cb, s, e0, e1);
+  if (used <= 1) return run_sgemm<2, 1, 8, 8>(db, q, out, D1, B, n_rb, n_kb, n_cb, s, e0, e1);
+  if (used <= 2) return run_sgemm<2, 2, 8, 8>(db, q, out, D1, B, n_rb, n_kb, n_cb, s, e0, e1);
+  return run_sgemm<2, 4, 8, 8>(db, q, out, D1, B, n_rb, n_kb, n_cb, s, e0, e1);
 }
 
 }  // namespace pir
