@@ -535,7 +535,7 @@ def main() -> int:
                     help="only run a plain 1 GiB device copy (for HBM counter scaling)")
     args = ap.parse_args()
     if args.gpus != 1:
-        print(json.dumps({"error": "this build runs on exactly one GPU; --gpus must be 1"}))
+        print(json.dumps({"error": "bench.py measures one GPU; --gpus must be 1"}))
         return 2
     if args.calibrate_copy:
         calibrate_copy()
