@@ -273,7 +273,8 @@ pir_status pir_tune_batch(pir_ctx *ctx, const pir_job *jobs, size_t n_jobs, pir_
 
 /* ---- continuous-batching server (Sec. 2.5 multi-client batching;
  * Sec. 4.4 stream-wise buffering).  The database's K*N (prime, slot) pairs are
- * cut into n_chunks ranges scanned round-robin, one range per step.  A query
+ * cut into n_chunks ranges [K N c / n_chunks, K N (c+1) / n_chunks) scanned
+ * round-robin, one range per step.  A query
  * is admitted at a step boundary into a free column slot (forward NTT and
  * limb packing into its own columns), takes part in every step's scan launch
  * with all other active queries, and finishes after n_chunks steps: inverse
@@ -300,12 +301,40 @@ pir_status pir_server_step(pir_server *srv, pir_stream stream, uint32_t *admitte
                            uint32_t *finished);
 
 /* *done = 1 once the ticket's answer is in its buffer (reported once; the
- * ticket is then forgotten), else 0.  INVALID_ARG for unknown tickets. */
+ * ticket is then forgotten), else 0.  INVALID_ARG for unknown tickets;
+ * DEVICE (reported once) for a ticket whose answer drain could not be
+ * launched.  A step whose admission or scan launch fails returns DEVICE and
+ * leaves the failed query queued and the range unscanned, so stepping again
+ * retries it. */
 pir_status pir_server_poll(pir_server *srv, uint64_t ticket, int *done);
 
 /* Admission limit after the budget, queries active and queued, next range. */
 pir_status pir_server_info(const pir_server *srv, uint32_t *max_batch, uint32_t *active,
                            uint32_t *queued, uint32_t *next_chunk);
+
+/* Capacity planning on the host (no device): the largest batch <= max_batch
+ * whose server state -- query limbs of every column slot, the answer state of
+ * every slot, one admission's NTT scratch -- fits in budget_bytes beside
+ * held_bytes already held (budget 0 = no cap), for a database of R x C
+ * polynomials under `params`.  *admitted = 0 if not even one fits;
+ * *state_bytes (may be NULL) receives that batch's state size.  This is the
+ * limit pir_server_create applies. */
+pir_status pir_server_capacity(const pir_params *params, uint32_t R, uint32_t C, size_t held_bytes,
+                               size_t budget_bytes, uint32_t max_batch, uint32_t *admitted,
+                               size_t *state_bytes);
+
+/* The server's schedule run on the host with a stand-in executor (no device),
+ * for tests and capacity planning.  n_slots = K*N slots cut into n_chunks
+ * ranges (1 <= n_chunks <= n_slots); submits[s] queries are submitted before
+ * step s (s < n_steps), numbered 0.. in submission order; n_queries = their
+ * sum.  For each query: admit_step, admit_slot (column slot) and finish_step
+ * (UINT32_MAX if it did not happen within n_steps).  cover (host,
+ * [n_queries][n_slots], may be NULL) counts how often each slot was scanned
+ * while the query was active: exactly 1 everywhere for a finished query. */
+pir_status pir_server_simulate(uint32_t max_batch, uint32_t n_slots, uint32_t n_chunks,
+                               const uint32_t *submits, uint32_t n_steps, uint32_t n_queries,
+                               uint32_t *admit_step, uint32_t *admit_slot, uint32_t *finish_step,
+                               uint32_t *cover);
 
 /* ---- measurement: per-stage kernel time with HIP events (off by default).
  * While enabled, pir_db_mul and pir_answer_batch time each profiled stage with

@@ -533,7 +533,7 @@ pir_status pir_db_load_ntt(pir_ctx *ctx, const pir_params *params, const uint8_t
   const uint32_t Rp = r_pad(R), Cp = c_pad(C);
   // + a 64 KiB tail: the batched kernel's padded contraction steps read past
   // the last atom of the last slot (their products meet zero query atoms)
-  const size_t bytes = (size_t)K * N * Rp * Cp * 4 + (64u << 10);
+  const size_t bytes = (size_t)K * N * Rp * Cp * 4 + kDbTailBytes;
   pir_db *db = new (std::nothrow) pir_db;
   if (!db) return fail(ctx, PIR_ERR_OUT_OF_MEMORY, "host allocation failed");
   db->ctx = ctx;

@@ -192,8 +192,10 @@ __global__ __launch_bounds__(kThreads) void k_lift_ntt(const uint8_t *__restrict
 // Modulus switching (Sec. 4.3 fuses it with the inverse NTT; App. D.5): the
 // coefficient x in [0, Q) with residues x0 mod q0 (and x1 mod q1) becomes the
 // nearest integer to x 2^bits / Q, reduced mod 2^bits.
-//  * CRT (Garner): y = (x1 - x0) q0^-1 mod q1, x = x0 + q0 y < Q < 2^56,
-//    with the exact fp64 product of mulmod_f64;
+//  * CRT (Garner): y = (x1 - x0) q0^-1 mod q1, x = x0 + q0 y < Q < 2^56.  The
+//    signed difference x1 - x0 (|x1 - x0| < 2^28, whatever the sizes of q0
+//    and q1) goes straight into the exact fp64 product of mulmod_f64, which
+//    reduces any integer operand below 2^53 to within 0.51 q1 of zero;
 //  * k = rint(x * (2^bits / Q)) in fp64 is within one of the nearest integer:
 //    its error is below 2^-19 on a value below 2^32;
 //  * the residual r = x 2^bits - k Q is computed in wrapping 64-bit integer
@@ -211,10 +213,8 @@ template <bool TWO>
 __device__ __forceinline__ uint32_t mod_switch(uint32_t x0, uint32_t x1, const MsArgs &m) {
   uint64_t x = x0;
   if constexpr (TWO) {
-    const uint32_t x0r = x0 >= m.q1 ? x0 - m.q1 : x0;  // x0 < q0 < 2 q1
-    uint32_t d = x1 + m.q1 - x0r;                       // < 2 q1
-    d = d >= m.q1 ? d - m.q1 : d;
-    const double r = mulmod_f64((double)d, m.c, m.q1d, m.inv_q1);  // |r| < 0.51 q1
+    const double d = (double)x1 - (double)x0;                      // |d| < 2^28
+    const double r = mulmod_f64(d, m.c, m.q1d, m.inv_q1);          // |r| < 0.51 q1
     const uint32_t y = (uint32_t)(int)(r < 0.0 ? r + m.q1d : r);
     x += (uint64_t)m.q0 * y;
   }

@@ -55,6 +55,10 @@ constexpr uint32_t kIB = 32;   // contraction indices i per atom
 constexpr uint32_t kRAlign = 64;
 constexpr uint32_t kCB = 8;    // query columns per atom
 
+// Bytes of padding after a database's last atom: the batched scan's padded
+// contraction steps may read (never use) atoms there.
+constexpr uint32_t kDbTailBytes = 64u << 10;
+
 inline uint32_t r_pad(uint32_t R) { return (R + kRAlign - 1) / kRAlign * kRAlign; }
 inline uint32_t c_pad(uint32_t C) { return (C + kJB - 1) / kJB * kJB; }
 

@@ -494,8 +494,9 @@ __global__ __launch_bounds__(256, OCC) void k_scan_mfma(const MfArgs args) {
   const uint32_t n_ib = db.n_ib, cbs = a.cb_stride;
   // Steps per item: n_ib rounded up to the ring depth, and at least as many
   // chunks as the staging looks ahead (two, three with LDS DMA), so that it
-  // never reaches past the next item.  Extra steps meet zero query atoms; their database reads
-  // stay within the allocation's tail padding (at most 7 atoms past the end).
+  // never reaches past the next item.  Extra steps meet zero query atoms; their
+  // database reads run at most S - n_ib atoms past the last row block of the
+  // last slot, which the launcher checks against the database's tail padding.
   const uint32_t S = (max(n_ib, (kDma ? 3 : 2) * kKCB) + D - 1) / D * D;
   const uint32_t nc = S / kKCB;  // chunks per item
   const uint32_t lane_off = lane * 16;
@@ -824,10 +825,16 @@ constexpr uint32_t kItemsPerBlock = 16, kMinBlocks = 1024;
 
 template <int JBW, int CBW, int D, int OCC>
 hipError_t run_mfma(const ScanJob *jobs, size_t n, hipStream_t s, hipEvent_t e0, hipEvent_t e1) {
+  constexpr uint32_t kAtomsChunk = kKCB * CBW;
+  constexpr bool kDma = 3 * kAtomsChunk * 64 * 16 * OCC <= 160 * 1024;  // as in the kernel
   MfArgs a{};
   uint32_t total = 0;
   for (size_t i = 0; i < n; ++i) {
     const ScanJob &job = jobs[i];
+    // the padded contraction steps past n_ib read database atoms beyond the
+    // last row block of the last slot: they must stay inside the tail padding
+    const uint32_t S = (std::max(job.db.n_ib, (kDma ? 3u : 2u) * kKCB) + D - 1) / D * D;
+    if ((S - job.db.n_ib) * kAtomBytes > kDbTailBytes) return hipErrorInvalidValue;
     MfJob &m = a.jobs[i];
     m.db = job.db;
     m.qatoms = job.qatoms;

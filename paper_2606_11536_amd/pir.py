@@ -82,6 +82,10 @@ SIGNATURES = {
     "pir_server_step": (ct.c_int, [_P, _P, _U32P, _U32P]),
     "pir_server_poll": (ct.c_int, [_P, ct.c_uint64, ct.POINTER(ct.c_int)]),
     "pir_server_info": (ct.c_int, [_P, _U32P, _U32P, _U32P, _U32P]),
+    "pir_server_capacity": (ct.c_int, [ct.POINTER(CParams), _U32, _U32, ct.c_size_t, ct.c_size_t,
+                                       _U32, _U32P, ct.POINTER(ct.c_size_t)]),
+    "pir_server_simulate": (ct.c_int, [_U32, _U32, _U32, _U32P, _U32, _U32, _U32P, _U32P, _U32P,
+                                       _U32P]),
     "pir_profile_enable": (ct.c_int, [_P, ct.c_int]),
     "pir_profile_read": (ct.c_int, [_P, _U32, ct.POINTER(ct.c_double),
                                     ct.POINTER(ct.c_uint64)]),
@@ -383,6 +387,31 @@ class Context:
 
 def scan_variants(B: int) -> int:
     return lib.pir_scan_variants(B)
+
+
+def server_capacity(params: Params, R: int, C: int, held_bytes: int, budget_bytes: int,
+                    max_batch: int) -> tuple[int, int]:
+    """(admitted batch, its state bytes) under an HBM budget (host only)."""
+    a, b = ct.c_uint32(), ct.c_size_t()
+    _check(lib.pir_server_capacity(ct.byref(params.c()), R, C, held_bytes, budget_bytes, max_batch,
+                                   ct.byref(a), ct.byref(b)))
+    return a.value, b.value
+
+
+def server_simulate(max_batch: int, n_slots: int, n_chunks: int, submits, cover: bool = True):
+    """The server's schedule on the host: returns (admit_step, admit_slot,
+    finish_step, cover) numpy arrays (cover [n_queries][n_slots] or None)."""
+    import numpy as np
+    sub = np.ascontiguousarray(submits, dtype=np.uint32)
+    nq = int(sub.sum())
+    a_step, a_slot, f_step = (np.empty(nq, dtype=np.uint32) for _ in range(3))
+    cov = np.empty((nq, n_slots), dtype=np.uint32) if cover else None
+    p = ct.POINTER(ct.c_uint32)
+    _check(lib.pir_server_simulate(max_batch, n_slots, n_chunks, sub.ctypes.data_as(p), len(sub), nq,
+                                   a_step.ctypes.data_as(p), a_slot.ctypes.data_as(p),
+                                   f_step.ctypes.data_as(p),
+                                   cov.ctypes.data_as(p) if cover else None))
+    return a_step, a_slot, f_step, cov
 
 
 class Server:

@@ -4,6 +4,7 @@ The fused kernel (inverse NTT per prime, CRT, nearest integer to x 2^bits / Q
 mod 2^bits) is compared word for word with the oracle:
 * uniform NTT-form residues, N in {1024, 2048, 4096}, one and two primes,
   bits in {29, 20, 32, 1}, a ragged polynomial count;
+* two primes of very different size (28 and 14 bits), in both orders;
 * at the size of a config-3 batch (32 queries x 1024 columns x 2 = 65536
   polynomials, N = 2048, two primes: 1 GiB in, 512 MiB out) on sampled
   polynomials;
@@ -49,6 +50,24 @@ def test_matches_oracle(ctx, log2n, K, bits):
     ctx.intt_modswitch(rg.pir_params(), src, out, bits)
     assert np.array_equal(to_host(out), oms.intt_switch(hat, rg.primes, rg.psis, bits))
     assert np.array_equal(to_host(src), hat)
+
+
+@pytest.mark.parametrize("order", [0, 1])
+@pytest.mark.parametrize("bits", [29, 32, 7])
+def test_unequal_primes_match_oracle(ctx, order, bits):
+    """A 28-bit prime beside a 14-bit one (both = 1 mod 2N at N = 1024): the CRT
+    step must not assume the primes are of similar size."""
+    from oracle import params as op
+    from pirtest import Ring
+    qs = [op.ntt_primes(1024, 1)[0], 12289]
+    qs = qs if order == 0 else qs[::-1]
+    rg = Ring(10, qs, [op.psi_min(1024, q) for q in qs], op.scale(qs, 256))
+    P = 29
+    hat = residues(np.random.default_rng(100 + order * 10 + bits), (P,), rg)
+    hat[0, :, :5] = np.array(qs, dtype=np.uint64)[:, None] - 1          # largest residues
+    out = empty_dev((P, rg.N))
+    ctx.intt_modswitch(rg.pir_params(), to_dev(hat), out, bits)
+    assert np.array_equal(to_host(out), oms.intt_switch(hat, rg.primes, rg.psis, bits))
 
 
 def test_full_batch_sampled(ctx):
