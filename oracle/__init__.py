@@ -21,6 +21,8 @@ Modules
             App. D.5) and decryption at the reduced modulus.
 ``scalar``  the scalar-HE database GEMM mod 2^32 (Sec. 4.1) and a toy
             SimplePIR round trip (Sec. 2).
+``pack``    Tiptoe-style ring packing of LWE ciphertexts into RLWE ones,
+            H C + (0|G) (App. C.1, Eq. tiptoe-rp; Sec. 3.5).
 
 All arithmetic is on exact integers (Python ints, or numpy uint64/int64 with
 every intermediate bounded below 2**63); nothing is approximated.

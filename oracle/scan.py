@@ -125,6 +125,42 @@ def weighted_rows(raw_rows: np.ndarray, r: np.ndarray, q: int) -> np.ndarray:
     return out
 
 
+def weighted_rows_multi(raw_rows: np.ndarray, rs: list[np.ndarray], primes: list[int]) -> np.ndarray:
+    """``weighted_rows`` for several (weights, prime) pairs in one pass over the rows.
+
+    Returns ``[V][R'][N]`` uint64 with entry ``[v][i] = sum_j rs[v][j] * DB[i][j] (mod primes[v])``.
+    The same exact float64 products as ``weighted_rows`` (14-bit halves of every
+    weight vector stacked into one matrix), so each row is converted once.
+    """
+    C = raw_rows.shape[1]
+    if C >= 1 << 31:
+        raise ValueError("C too large for the exact float64 bound")
+    V = len(rs)
+    qq = [np.uint64(q) for q in primes]
+    red = [np.asarray(r, dtype=np.uint64) % q for r, q in zip(rs, qq)]
+    W = np.stack([(r & np.uint64(0x3FFF)).astype(np.float64) for r in red] +
+                 [(r >> np.uint64(14)).astype(np.float64) for r in red])        # [2V][C]
+    out = np.empty((V, raw_rows.shape[0], raw_rows.shape[2]), dtype=np.uint64)
+    for ii in range(raw_rows.shape[0]):
+        s = (W @ raw_rows[ii].astype(np.float64)).astype(np.uint64)           # [2V][N]
+        for v in range(V):
+            lo, hi = s[v] % qq[v], s[V + v] % qq[v]
+            out[v, ii] = (lo + (hi << np.uint64(14)) % qq[v]) % qq[v]
+    return out
+
+
+def freivalds_expected_from_rows(w: np.ndarray, q_hat: np.ndarray, k: int, q: int,
+                                 psi: int) -> np.ndarray:
+    """``freivalds_expected`` from weighted rows ``w`` = ``weighted_rows(raw, r, q)`` (``[R][N]``)."""
+    qq = np.uint64(q)
+    w_hat = _ntt.ntt(w, q, psi)
+    B = q_hat.shape[0]
+    acc = np.zeros((B, 2, w.shape[1]), dtype=np.uint64)
+    for i in range(w.shape[0]):
+        acc = (acc + w_hat[i][None, None, :] * q_hat[:, i, :, k, :]) % qq
+    return acc
+
+
 def freivalds_expected(raw: np.ndarray, q_hat: np.ndarray, r: np.ndarray, k: int,
                        q: int, psi: int) -> np.ndarray:
     """``sum_j r_j Y[b][j][c][k][t]`` computed without ``Y``, by linearity of the NTT.

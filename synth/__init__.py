@@ -21,7 +21,10 @@ drawing the others:
 * queried indices             -> ``[seed, TAG_INDEX]``: ``B`` integers in ``[0, R)``;
 * uniform ciphertext stand-ins -> ``[seed, TAG_UNIFORM, b, i]``: used where a
   workload needs ciphertext-shaped data without a key (an RLWE ciphertext is
-  indistinguishable from uniform, so the scan sees the same distribution).
+  indistinguishable from uniform, so the scan sees the same distribution);
+* LWE operands of ring packing: the ``a``-part matrix in blocks of 1024 rows
+  ``[seed, TAG_LWE_A, block]``, client ``beta``'s ``b``-parts
+  ``[seed, TAG_LWE_B, beta]`` and LWE secret ``[seed, TAG_LWE_SECRET, beta]``.
 
 The error clip ``|e| <= 19`` is the fresh-noise bound ``|e| < 6*sigma`` with
 ``sigma = 3.2`` (cryptographic background, LWE paragraph), applied to RLWE too.
@@ -40,6 +43,9 @@ TAG_UNIFORM = 0xBE
 TAG_SIZES = 0x51
 TAG_FREIVALDS = 0xF5
 TAG_ARRIVALS = 0xA7
+TAG_LWE_A = 0x1A
+TAG_LWE_B = 0x1B
+TAG_LWE_SECRET = 0x15
 
 SIGMA = 3.2
 ERROR_CLIP = 19
@@ -152,6 +158,29 @@ def uniform_query(seed: int, b: int, R: int, primes: list[int], N: int) -> np.nd
 def batch_sizes(seed: int, n_db: int, lo: int = 1, hi: int = 64) -> np.ndarray:
     """Per-database query counts for a multi-database batch: int64 in ``[lo, hi]``."""
     return _rng(seed, TAG_SIZES).integers(lo, hi + 1, size=n_db, dtype=np.int64)
+
+
+def lwe_matrix(seed: int, D1: int, n: int, p: int) -> np.ndarray:
+    """The ``a``-parts of ``D1`` LWE ciphertexts (or a hint): ``[D1][n]`` uint32 uniform in
+    ``[0, p)``, ``p <= 2**32``; rows drawn in blocks of 1024 from ``[seed, TAG_LWE_A, block]``."""
+    out = np.empty((D1, n), dtype=np.uint32)
+    for r0 in range(0, D1, 1024):
+        r1 = min(D1, r0 + 1024)
+        out[r0:r1] = _rng(seed, TAG_LWE_A, r0 // 1024).integers(0, p, size=(r1 - r0, n),
+                                                                 dtype=np.uint64)
+    return out
+
+
+def lwe_offsets(seed: int, B: int, D1: int, p: int) -> np.ndarray:
+    """The ``b``-parts of client ``beta``'s ``D1`` LWE ciphertexts, ``beta < B``: ``[B][D1]``
+    uint32 uniform in ``[0, p)``."""
+    return np.stack([_rng(seed, TAG_LWE_B, beta).integers(0, p, size=D1, dtype=np.uint64)
+                     for beta in range(B)]).astype(np.uint32)
+
+
+def lwe_secret(seed: int, beta: int, n: int) -> np.ndarray:
+    """Client ``beta``'s LWE secret: ``n`` int64 values in {-1, 0, 1}."""
+    return _rng(seed, TAG_LWE_SECRET, beta).integers(-1, 2, size=n, dtype=np.int64)
 
 
 def freivalds_vector(seed: int, draw: int, C: int, q: int) -> np.ndarray:

@@ -131,3 +131,38 @@ def test_freivalds_identity_and_planted_flip():
             assert np.array_equal(scan.freivalds_observed(y, r, k, q), exp)
             caught = not np.array_equal(scan.freivalds_observed(bad, r, k, q), exp)
             assert caught == (k == 1)
+
+
+def test_weighted_rows_multi_brute_force():
+    """Several weight vectors and primes in one pass equal sum_j r_j DB[i][j] mod q
+    computed with Python integers, including the largest weights q - 1."""
+    N, R, C = 8, 5, 37
+    qs = params.ntt_primes(16, 2) + [12289]
+    raw = synth.db_bytes(8, R, C, N)
+    raw[0] = 255
+    rng = np.random.default_rng(3)
+    rs = [rng.integers(0, q, size=C, dtype=np.uint64) for q in qs]
+    rs.append(np.full(C, qs[0] - 1, dtype=np.uint64))
+    ps = qs + [qs[0]]
+    got = scan.weighted_rows_multi(raw, rs, ps)
+    for v, (r, q) in enumerate(zip(rs, ps)):
+        for i in range(R):
+            for n in range(N):
+                exp = sum(int(r[j]) * int(raw[i, j, n]) for j in range(C)) % q
+                assert int(got[v, i, n]) == exp
+        assert np.array_equal(got[v], scan.weighted_rows(raw, r, q))
+
+
+def test_freivalds_from_rows_equals_direct():
+    N, R, C, B = 64, 6, 9, 3
+    qs, psis = _setup(N, 2)
+    raw = synth.db_bytes(5, R, C, N)
+    rng = np.random.default_rng(11)
+    qh = np.stack([rng.integers(0, q, size=(B, R, 2, N)) for q in qs], axis=3).astype(np.uint64)
+    y = scan.db_mul(scan.db_ntt(raw, qs, psis), qh, qs)
+    rs = [synth.freivalds_vector(5, d, C, q) for q in qs for d in range(2)]
+    w = scan.weighted_rows_multi(raw, rs, [q for q in qs for _ in range(2)])
+    for v, r in enumerate(rs):
+        k = v // 2
+        exp = scan.freivalds_expected_from_rows(w[v], qh, k, qs[k], psis[k])
+        assert np.array_equal(exp, scan.freivalds_observed(y, r, k, qs[k]))
