@@ -1,19 +1,23 @@
 """Benchmark of the RLWE-PIR first-dimension scan on one MI355X.
 
 One step = one pass of the whole online hot path over one batch of queries,
-with the database and the queries already resident in HBM:
-forward NTT of the queries, their transposition into scan tiles, the
-database scan, and the inverse NTT of the answers (pir_answer_batch).
+with the database and the queries already resident in HBM: forward NTT of
+the queries, their transposition into scan tiles, the database scan, the
+answer transposition and the inverse NTT (pir_answer_batch).
 
 Metric: DB-scan GB/s = raw database bytes (R*C*N, one byte per plaintext
-coefficient) x queries / wall time, decimal GB.  The roofline object reports
-the scan kernel's algorithmic HBM bytes per launch divided by its average
-launch time, measured with HIP events on the launch stream inside the
-timed region.  The CPU baseline times the oracle on a bounded sample of the
-same workload on this host.
+coefficient) x queries / wall time, decimal GB.
 
-Default workload: N=2048, two 28-bit primes, 512 x 256 database
-(256 MiB raw, 2 GiB NTT form), one query per step.
+Default workload (the headline): N=2048, two 28-bit primes, a 4096 x 2048
+database (16 GiB raw, 128 GiB NTT form).  The timed steps are batches of
+128 queries in one call; beside them the same database answers one query
+per call (B=1), and the continuous-batching server runs Poisson arrivals
+for p50/p99 latency.  The roofline object covers the batched scan kernel
+(int8 matrix-core bound); `batch1_config` holds the batch-1 scan of the
+512 x 256 database (256 MiB raw), which is HBM-bound.  Kernel times come
+from HIP events the scan launch records itself, on the launch stream,
+inside the timed region.  The CPU baseline times the oracle on a bounded
+sample of the same workload on this host.
 """
 
 from __future__ import annotations
@@ -34,6 +38,12 @@ import synth  # noqa: E402
 
 METRIC = "DB-scan GB/s (raw DB bytes×queries/s), batched vs B=1; p50/p99 query latency"
 HBM_PEAK_GBS = 8000.0
+INT8_PEAK_TOPS = 5000.0   # dense int8 matrix-core peak of MI355X (TOP/s)
+LIMB_MACS = 16            # int8 MACs per modular MAC: 4 x 4 seven-bit limbs
+
+# headline: batched and batch-1 scans and serving on the 16 GiB-raw database
+HEADLINE = dict(log2n=11, K=2, R=4096, C=2048, B=128, pool=16, max_batch=128, n_chunks=64,
+                rates=[100, 500, 2000])
 
 WORKLOADS = {
     # name: (log2n, K, R, C, B)
@@ -51,6 +61,10 @@ DRAIN = dict(log2n=11, K=2, polys=32 * 1024 * 2, bits=29)
 # scalar-HE database GEMM mod 2^32: D1 x D0 int8 database (16 GiB, the paper's
 # D0 = 65536 words per query), one query and a batch of 32
 SCALAR = dict(D1=1 << 18, D0=1 << 16, batches=[1, 16, 32])
+# ring packing of the scalar GEMM's answers: D1 LWE ciphertexts per client
+# (the 2^18 rows of the 16 GiB scalar database), LWE dimension n = 1280,
+# packed into RLWE ciphertexts of N = 4096 under two primes, p = 2^18
+PACK = dict(log2n=12, K=2, D1=1 << 18, n=1280, p_log2=18, B=32)
 # three databases of uneven shape in one batch: (log2n, K, R, C)
 MULTIDB = [(12, 2, 1024, 512), (11, 2, 3000, 700), (11, 2, 256, 4096)]
 
@@ -59,9 +73,9 @@ KERNEL_SOURCES = ["paper_2606_11536_amd/csrc/scan.hip", "paper_2606_11536_amd/cs
                   "paper_2606_11536_amd/csrc/pir_internal.h"]
 
 
-def measured_traffic(kernel: str, workload: str):
-    """HBM bytes per launch from profiles/traffic.json, or None if absent or if the
-    kernel sources changed since the counters were taken."""
+def _profile_entry(kernel: str, workload: str):
+    """The entry of profiles/traffic.json for (kernel, workload), or None if absent or
+    if the kernel sources changed since the counters were taken."""
     import hashlib
     try:
         entries = json.load(open(os.path.join(ROOT, "profiles", "traffic.json")))["entries"]
@@ -72,8 +86,20 @@ def measured_traffic(kernel: str, workload: str):
         h.update(open(os.path.join(ROOT, f), "rb").read())
     for e in entries:
         if e["kernel"] == kernel and e["workload"] == workload and e["source_sha256"] == h.hexdigest():
-            return e["bytes_per_launch"]
+            return e
     return None
+
+
+def measured_traffic(kernel: str, workload: str):
+    """HBM bytes per launch from the committed counter runs (None if stale or absent)."""
+    e = _profile_entry(kernel, workload)
+    return e.get("bytes_per_launch") if e else None
+
+
+def measured_mfma(kernel: str, workload: str):
+    """Matrix-core busy fraction from the committed counter runs (None if stale or absent)."""
+    e = _profile_entry(kernel, workload)
+    return e.get("mfma") if e else None
 
 
 def log(msg: str) -> None:
@@ -84,6 +110,38 @@ def scan_alg_bytes(log2n, K, R, C, B) -> int:
     """Algorithmic HBM bytes of one scan launch: NTT-form DB once, B queries, B answers."""
     N = 1 << log2n
     return R * C * N * K * 4 + B * R * 2 * N * K * 4 + B * C * 2 * N * K * 4
+
+
+def scan_mod_macs(log2n, K, R, C, B) -> int:
+    """Modular multiply-adds of one scan: R x C x 2B per (prime, slot)."""
+    return R * C * 2 * B * K * (1 << log2n)
+
+
+def hbm_roofline(kernel, log2n, K, R, C, B, avg_ms, traffic=None) -> dict:
+    alg = scan_alg_bytes(log2n, K, R, C, B)
+    achieved = alg / (avg_ms * 1e-3) / 1e9
+    return {"bound": "hbm", "kernel": kernel, "achieved": round(achieved, 2), "peak": HBM_PEAK_GBS,
+            "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
+            "alg_bytes_per_launch": alg, "avg_launch_ms": round(avg_ms, 5)}
+
+
+def mfma_roofline(kernel, log2n, K, R, C, B, avg_ms, traffic=None, mfma_busy=None) -> dict:
+    """The batched scan against the int8 matrix-core peak: each modular MAC is
+    LIMB_MACS int8 MACs (2 ops each) on the matrix cores; beside it the same
+    launch's algorithmic HBM rate."""
+    macs = scan_mod_macs(log2n, K, R, C, B)
+    ops = 2 * LIMB_MACS * macs
+    tops = ops / (avg_ms * 1e-3) / 1e12
+    alg = scan_alg_bytes(log2n, K, R, C, B)
+    gbs = alg / (avg_ms * 1e-3) / 1e9
+    return {"bound": "mfma", "kernel": kernel, "achieved": round(tops, 2), "peak": INT8_PEAK_TOPS,
+            "unit": "TOP/s (int8)", "frac": round(tops / INT8_PEAK_TOPS, 4), "traffic": traffic,
+            "int8_ops_per_launch": ops, "mod_macs_per_launch": macs,
+            "ops_what": f"{LIMB_MACS} int8 MACs (4 x 4 seven-bit limbs) per modular MAC, 2 ops per MAC",
+            "mfma_busy": mfma_busy,
+            "hbm": {"achieved": round(gbs, 2), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                    "frac": round(gbs / HBM_PEAK_GBS, 4), "alg_bytes_per_launch": alg},
+            "avg_launch_ms": round(avg_ms, 5)}
 
 
 def _oracle_sample(log2n, K, R, cs, primes, seed, min_s, max_reps):
@@ -189,48 +247,22 @@ def calibrate_copy(nbytes: int = 1 << 30, reps: int = 3) -> None:
                       "reps": reps}), flush=True)
 
 
-def serve(args) -> dict:
-    """Continuous batching on the 16 GiB-raw database under Poisson arrivals."""
+def serve_rates(pir, ctx, db, pool, max_batch, n_chunks, rates, args):
+    """Poisson arrivals at each rate against a continuous-batching server; the
+    pool's queries are submitted round-robin.  Latency runs from a request's
+    arrival to its completion event."""
     import collections
 
     import torch
-
-    from paper_2606_11536_amd import pir
-    cfg = SERVE
-    log2n, K, R, C = cfg["log2n"], cfg["K"], cfg["R"], cfg["C"]
-    N = 1 << log2n
-    primes = pir.find_primes(log2n, K, 28)
-    params = pir.Params(log2n, primes, 8)
+    if not rates:
+        return [], max_batch
+    C, K, N = db.C, db.params.K, db.params.N
     dev = torch.device("cuda:0")
-    t = time.perf_counter()
-    raw = synth.db_bytes_parallel(args.seed, R, C, N)
-    log(f"[serve] 16 GiB database generated in {time.perf_counter() - t:.1f} s")
-    ctx = pir.Context(0)
-    t = time.perf_counter()
-    db = ctx.load_db(params, raw, R, C)
-    load_s = time.perf_counter() - t
-    del raw
-    log(f"[serve] database loaded in {load_s:.1f} s ({db.device_bytes / 2**30:.0f} GiB NTT form)")
-    pool = [torch.from_numpy(synth.uniform_query_parallel(args.seed, b, R, primes, N).view(np.int32))
-            .to(dev) for b in range(cfg["pool"])]
-    # batch-1 reference on the same database: one query per pir_answer_batch call
-    ans1 = torch.empty((1, C, 2, K, N), dtype=torch.int32, device=dev)
-    q1 = pool[0].view(1, R, 2, K, N)
-    ctx.tune(db, 1)
-    ctx.answer_batch([(db, 1, q1, ans1)])
-    torch.cuda.synchronize()
-    t = time.perf_counter()
-    n1 = 5
-    for _ in range(n1):
-        ctx.answer_batch([(db, 1, q1, ans1)])
-    torch.cuda.synchronize()
-    b1_ms = (time.perf_counter() - t) * 1e3 / n1
-    log(f"[serve] batch-1 pass: {b1_ms:.2f} ms/query")
-    srv = pir.Server(ctx, db, cfg["max_batch"], cfg["n_chunks"])
-    n_out = cfg["max_batch"] + 64
+    srv = pir.Server(ctx, db, max_batch, n_chunks)
+    n_out = srv.info()["max_batch"] + 64
     outs = [torch.empty((C, 2, K, N), dtype=torch.int32, device=dev) for _ in range(n_out)]
     results = []
-    for lam in cfg["rates"]:
+    for lam in rates:
         n_req = int(max(100, min(lam * args.serve_seconds, args.serve_max_requests)))
         arr = synth.poisson_arrivals(args.seed, float(lam), n_req)
         free = collections.deque(range(n_out))
@@ -273,7 +305,76 @@ def serve(args) -> dict:
              "max_active": int(max(batch)) if batch else 0, "steps": steps}
         log(f"[serve] {r}")
         results.append(r)
+    mb = srv.info()["max_batch"]
     srv.close()
+    del outs
+    return results, mb
+
+
+def load_db(pir, ctx, log2n, K, R, C, seed, parallel=True):
+    """The seeded synthetic database, lifted, transformed and tiled on the device."""
+    N = 1 << log2n
+    primes = pir.find_primes(log2n, K, 28)
+    t = time.perf_counter()
+    raw = (synth.db_bytes_parallel if parallel else synth.db_bytes)(seed, R, C, N)
+    gen_s = time.perf_counter() - t
+    t = time.perf_counter()
+    db = ctx.load_db(pir.Params(log2n, primes, 8), raw, R, C)
+    load_s = time.perf_counter() - t
+    del raw
+    log(f"[bench] database N={N} {R}x{C}: generated in {gen_s:.1f} s, loaded (lift+NTT+tiling) "
+        f"in {load_s:.2f} s, {db.device_bytes / 2**30:.2f} GiB NTT form")
+    return db, primes, load_s
+
+
+def time_steps(ctx, jobs, steps, warmup, stage_pass=True):
+    """Warm up, then time `steps` calls of answer_batch(jobs) with only the scan's
+    launch-recorded events on; then a separate pass with every stage timed."""
+    import torch
+    for _ in range(warmup):
+        ctx.answer_batch(jobs)
+    torch.cuda.synchronize()
+    ctx.profile(True, stages=("scan",))
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        ctx.answer_batch(jobs)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    scan_ms, scan_n = ctx.profile_read("scan")
+    stage = None
+    if stage_pass:
+        ctx.profile(True)
+        for _ in range(max(1, min(steps, 5))):
+            ctx.answer_batch(jobs)
+        stage = {st: ctx.profile_read(st) for st in ("ntt", "pack", "scan", "unpack", "intt")}
+        stage = {st: round(v[0] / max(v[1], 1), 5) for st, v in stage.items()}
+    ctx.profile(False)
+    return wall, scan_ms / max(scan_n, 1), stage
+
+
+def serve(args) -> dict:
+    """Continuous batching on the 16 GiB-raw database under Poisson arrivals."""
+    import torch
+
+    from paper_2606_11536_amd import pir
+    cfg = SERVE
+    log2n, K, R, C = cfg["log2n"], cfg["K"], cfg["R"], cfg["C"]
+    N = 1 << log2n
+    dev = torch.device("cuda:0")
+    ctx = pir.Context(0)
+    db, primes, load_s = load_db(pir, ctx, log2n, K, R, C, args.seed)
+    pool = [torch.from_numpy(synth.uniform_query_parallel(args.seed, b, R, primes, N).view(np.int32))
+            .to(dev) for b in range(cfg["pool"])]
+    # batch-1 reference on the same database: one query per pir_answer_batch call
+    ans1 = torch.empty((1, C, 2, K, N), dtype=torch.int32, device=dev)
+    q1 = pool[0].view(1, R, 2, K, N)
+    ctx.tune(db, 1)
+    wall, _, _ = time_steps(ctx, [(db, 1, q1, ans1)], 5, 1, stage_pass=False)
+    b1_ms = wall * 1e3 / 5
+    log(f"[serve] batch-1 pass: {b1_ms:.2f} ms/query")
+    results, mb = serve_rates(pir, ctx, db, pool, cfg["max_batch"], cfg["n_chunks"], cfg["rates"],
+                              args)
     best = max(r["achieved_qps"] for r in results)
     raw_bytes = R * C * N
     out = {
@@ -284,7 +385,7 @@ def serve(args) -> dict:
         "config": {"workload": (f"serving: N={N}, {K} primes < 2^28, p=2^8, device-resident DB "
                                 f"R={R} x C={C} ({raw_bytes / 2**30:.0f} GiB raw, "
                                 f"{db.device_bytes / 2**30:.0f} GiB NTT form), Poisson arrivals, "
-                                f"continuous batching up to {srv_max(cfg)} queries, "
+                                f"continuous batching up to {mb} queries, "
                                 f"{cfg['n_chunks']} slot ranges per lap, pool of {cfg['pool']} "
                                 f"uniform ciphertext-shaped queries"),
                    "N": N, "primes": primes, "R": R, "C": C, "db_load_s": round(load_s, 2)},
@@ -295,6 +396,114 @@ def serve(args) -> dict:
     }
     db.free()
     ctx.close()
+    return out
+
+
+def headline(args, cpu) -> dict:
+    """Batched (B=128) and batch-1 scans and serving on the 16 GiB-raw database,
+    plus the batch-1 scan of the 512 x 256 database for its HBM roofline."""
+    import torch
+
+    from paper_2606_11536_amd import pir
+    cfg = HEADLINE
+    log2n, K, R, C, B = cfg["log2n"], cfg["K"], cfg["R"], cfg["C"], cfg["B"]
+    N = 1 << log2n
+    dev = torch.device("cuda:0")
+    ctx = pir.Context(0)
+    db, primes, load_s = load_db(pir, ctx, log2n, K, R, C, args.seed)
+    t = time.perf_counter()
+    pool = [torch.from_numpy(synth.uniform_query_parallel(args.seed, b, R, primes, N).view(np.int32))
+            .to(dev) for b in range(cfg["pool"])]
+    log(f"[bench] {len(pool)} ciphertext-shaped queries drawn in {time.perf_counter() - t:.1f} s")
+    raw_bytes = R * C * N
+
+    # batched: B queries per call (the pool repeated), every one computed separately
+    qb = torch.empty((B, R, 2, K, N), dtype=torch.int32, device=dev)
+    for b in range(B):
+        qb[b].copy_(pool[b % len(pool)])
+    ansb = torch.empty((B, C, 2, K, N), dtype=torch.int32, device=dev)
+    tune_b = None if args.no_tune else ctx.tune(db, B)
+    log(f"[bench] tuned B={B}: {tune_b}")
+    wall, scan_b_ms, stage = time_steps(ctx, [(db, B, qb, ansb)], args.steps, args.warmup)
+    ms_b = wall * 1e3 / args.steps
+    value = raw_bytes * B * args.steps / wall / 1e9
+    kernel_b = ctx.scan_kernel(db, B)
+    log(f"[bench] B={B}: {ms_b:.3f} ms/step, scan {scan_b_ms:.3f} ms, {value:.1f} GB/s raw")
+    del qb, ansb
+    torch.cuda.empty_cache()
+
+    # batch-1 on the same database
+    q1 = pool[0].view(1, R, 2, K, N)
+    ans1 = torch.empty((1, C, 2, K, N), dtype=torch.int32, device=dev)
+    tune_1 = None if args.no_tune else ctx.tune(db, 1)
+    n1 = max(10, args.steps)
+    wall1, scan_1_ms, stage1 = time_steps(ctx, [(db, 1, q1, ans1)], n1, max(1, args.warmup))
+    ms_1 = wall1 * 1e3 / n1
+    value_1 = raw_bytes * n1 / wall1 / 1e9
+    kernel_1 = ctx.scan_kernel(db, 1)
+    log(f"[bench] B=1: {ms_1:.3f} ms/query, scan {scan_1_ms:.3f} ms, {value_1:.1f} GB/s raw")
+    del ans1
+
+    # serving: continuous batching under Poisson arrivals
+    serving, mb = serve_rates(pir, ctx, db, pool, cfg["max_batch"], cfg["n_chunks"],
+                              [] if args.no_serving else cfg["rates"], args)
+    sat = max([r["achieved_qps"] for r in serving] or [float("nan")])
+    del pool
+    db_bytes = db.device_bytes
+    db.free()
+    torch.cuda.empty_cache()
+
+    # the batch-1 scan of the 512 x 256 database: the HBM-bound kernel
+    b1c = scan_workload(pir, ctx, "batch1", args)
+    ctx.close()
+
+    out = {
+        "metric": METRIC,
+        "value": round(value, 3),
+        "unit": "GB/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms_b, 4),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "u32",
+        "data": "synthetic",
+        "config": {
+            "workload": (f"batched scan of a 16 GiB-raw database: N={N}, {K} primes < 2^28, p=2^8, "
+                         f"DB R={R} x C={C} ({raw_bytes / 2**30:.0f} GiB raw, "
+                         f"{db_bytes / 2**30:.0f} GiB NTT form), B={B} uniform ciphertext-shaped "
+                         f"queries per step (NTT, pack, scan, unpack, INTT); B=1 and "
+                         f"continuous-batching serving on the same database"),
+            "N": N, "primes": primes, "R": R, "C": C, "B": B,
+            "raw_db_bytes": raw_bytes, "ntt_db_bytes": db_bytes, "db_load_s": round(load_s, 2),
+        },
+        "queries_per_s": round(B * 1e3 / ms_b, 2),
+        "speedup_vs_batch1": round(value / value_1, 2),
+        "batch1": {"value": round(value_1, 3), "unit": "GB/s", "ms_per_query": round(ms_1, 4),
+                   "queries_per_s": round(1e3 / ms_1, 2), "steps": n1, "kernel": kernel_1,
+                   "stage_ms": stage1, "scan_tuning": tune_1,
+                   "roofline": hbm_roofline(kernel_1, log2n, K, R, C, 1, scan_1_ms,
+                                            measured_traffic(kernel_1, "headline_b1"))},
+        "serving": {"max_batch": mb, "n_chunks": cfg["n_chunks"], "rates": serving,
+                    "saturation_qps": sat,
+                    "saturation_GBps": round(raw_bytes * sat / 1e9, 3),
+                    "speedup_vs_batch1": round(sat * ms_1 / 1e3, 2),
+                    "latency_what": "arrival to the completion event of the query's INTT"},
+        "latency_ms": ({"p50": serving[0]["p50_ms"], "p99": serving[0]["p99_ms"],
+                        "what": f"serving at {serving[0]['offered_qps']} q/s offered"}
+                       if serving else None),
+        "stage_ms": stage,
+        "stage_ms_what": "a separate pass after the timed steps with every stage bracketed by events",
+        "scan_tuning": tune_b,
+        "roofline": mfma_roofline(kernel_b, log2n, K, R, C, B, scan_b_ms,
+                                  measured_traffic(kernel_b, "headline"),
+                                  measured_mfma(kernel_b, "headline")),
+        "batch1_config": b1c,
+    }
+    if cpu is not None:
+        out["cpu_baseline"] = cpu
     return out
 
 
@@ -458,6 +667,94 @@ def scalar(args) -> dict:
     return res
 
 
+def pack(args) -> dict:
+    """Ring packing (pir_pack): B clients' D1 LWE ciphertexts each into RLWE ones."""
+    import torch
+
+    from paper_2606_11536_amd import pir
+    cfg = PACK
+    log2n, K, D1, n, plog, B = (cfg[k] for k in ("log2n", "K", "D1", "n", "p_log2", "B"))
+    N = 1 << log2n
+    Cp = -(-D1 // N)
+    cpu = None
+    if not args.no_cpu_baseline:
+        from oracle import pack as opk
+        from oracle import params as op
+        primes_o = op.ntt_primes(N, K)
+        psis = [op.psi_min(N, q) for q in primes_o]
+        rows = N                                        # one chunk of one client
+        A_s = synth.lwe_matrix(args.seed, rows, n, 1 << plog)
+        b_s = synth.lwe_offsets(args.seed, 1, rows, 1 << plog)
+        ct_s = synth.uniform_query(args.seed, 0, n, primes_o, N)[None].astype(np.uint64)
+        t = time.perf_counter()
+        opk.pack(A_s, b_s, ct_s, primes_o, psis, 1 << plog)
+        sec = time.perf_counter() - t
+        cpu = {"value": round(rows / sec, 2), "unit": "LWE ciphertexts/s", "cores": 1,
+               "kind": "oracle",
+               "sample": f"oracle packing of one chunk ({rows} LWE ciphertexts, n={n}) of one "
+                         f"client through the NTT, in {sec:.2f} s on one core"}
+    ctx = pir.Context(0)
+    primes = pir.find_primes(log2n, K, 28)
+    params = pir.Params(log2n, primes, plog)
+    dev = torch.device("cuda:0")
+    gen = torch.Generator(device="cuda").manual_seed(args.seed)
+    A = torch.randint(0, 1 << plog, (D1, n), generator=gen, device=dev, dtype=torch.int32)
+    t = time.perf_counter()
+    H = ctx.load_pack(params, A, D1, n)
+    torch.cuda.synchronize()
+    load_s = time.perf_counter() - t
+    del A
+    torch.cuda.empty_cache()
+    sp = torch.empty((B, n, 2, K, N), dtype=torch.int32, device=dev)
+    for k, q in enumerate(primes):
+        sp[:, :, :, k].copy_(torch.randint(0, q, (B, n, 2, N), generator=gen, device=dev,
+                                           dtype=torch.int64).to(torch.int32))
+    b = torch.randint(0, 1 << plog, (B, D1), generator=gen, device=dev, dtype=torch.int32)
+    out = torch.empty((B, Cp, 2, K, N), dtype=torch.int32, device=dev)
+    tune = None if args.no_tune else ctx.tune(H, B)
+    for _ in range(args.warmup):
+        ctx.pack(H, B, sp, b, out)
+    torch.cuda.synchronize()
+    ctx.profile(True, stages=("scan",))
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        ctx.pack(H, B, sp, b, out)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    scan_ms, scan_n = ctx.profile_read("scan")
+    ctx.profile(True)
+    for _ in range(max(1, min(args.steps, 5))):
+        ctx.pack(H, B, sp, b, out)
+    stage = {st: ctx.profile_read(st) for st in ("ntt", "pack", "scan", "unpack", "intt")}
+    stage = {st: round(v[0] / max(v[1], 1), 5) for st, v in stage.items()}
+    ctx.profile(False)
+    ms = wall * 1e3 / args.steps
+    scan_avg = scan_ms / max(scan_n, 1)
+    kernel = ctx.scan_kernel(H, B)
+    res = {
+        "metric": "ring packing: LWE ciphertexts packed into RLWE ciphertexts per second",
+        "value": round(B * D1 / (ms * 1e-3), 1), "unit": "LWE ciphertexts/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(ms, 4),
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "u32",
+        "data": "synthetic",
+        "config": {"workload": (f"ring packing H C + (0|G): D1={D1} LWE ciphertexts per client, "
+                                f"n={n}, p=2^{plog}, N={N}, {K} primes < 2^28, {Cp} RLWE "
+                                f"ciphertexts per client, B={B} clients (special ciphertexts "
+                                f"and offsets uniform)"),
+                   "N": N, "primes": primes, "D1": D1, "n": n, "B": B, "chunks": Cp,
+                   "hint_load_s": round(load_s, 3)},
+        "stage_ms": stage,
+        "scan_tuning": tune,
+        "roofline": hbm_roofline(kernel, log2n, K, n, Cp, B, scan_avg,
+                                 measured_traffic(kernel, "pack")),
+    }
+    if cpu is not None:
+        res["cpu_baseline"] = cpu
+    H.free()
+    ctx.close()
+    return res
+
+
 def multidb(args) -> dict:
     """Three uneven databases, 1..64 queries each, one fused batch, HIP-graph replays."""
     import torch
@@ -516,62 +813,13 @@ def multidb(args) -> dict:
     return out
 
 
-def main() -> int:
-    ap = argparse.ArgumentParser()
-    ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=50)
-    ap.add_argument("--warmup", type=int, default=5)
-    ap.add_argument("--workload", default="batch1",
-                    choices=sorted(WORKLOADS) + ["serving", "multidb", "drain", "scalar"])
-    ap.add_argument("--serve-seconds", type=float, default=3.0)
-    ap.add_argument("--serve-max-requests", type=int, default=1500)
-    ap.add_argument("--seed", type=int, default=0)
-    ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--latency-steps", type=int, default=50)
-    ap.add_argument("--no-tune", action="store_true", help="use the default scan variant")
-    ap.add_argument("--switch-bits", type=int, default=0,
-                    help="drain the answers with modulus switching to 2^bits (0: plain INTT)")
-    ap.add_argument("--calibrate-copy", action="store_true",
-                    help="only run a plain 1 GiB device copy (for HBM counter scaling)")
-    args = ap.parse_args()
-    if args.gpus != 1:
-        print(json.dumps({"error": "bench.py measures one GPU; --gpus must be 1"}))
-        return 2
-    if args.calibrate_copy:
-        calibrate_copy()
-        return 0
-    if args.workload in ("serving", "multidb", "drain", "scalar"):
-        fn = {"serving": serve, "multidb": multidb, "drain": drain, "scalar": scalar}[args.workload]
-        print(json.dumps(fn(args)), flush=True)
-        return 0
-
-    log2n, K, R, C, B = WORKLOADS[args.workload]
-    cpu = None
-    if not args.no_cpu_baseline:
-        # before anything touches the GPU: the all-core leg forks worker processes
-        from oracle import params as op
-        log("[bench] timing the CPU oracle on a bounded sample")
-        cpu = cpu_baseline(log2n, K, R, C, op.ntt_primes(1 << log2n, K), args.seed)
-
+def scan_workload(pir, ctx, name, args) -> dict:
+    """One of WORKLOADS through pir_answer_batch on its own database."""
     import torch
-
-    from paper_2606_11536_amd import pir
-
+    log2n, K, R, C, B = WORKLOADS[name]
     N = 1 << log2n
-    primes = pir.find_primes(log2n, K, 28)
-    params = pir.Params(log2n, primes, 8)
     dev = torch.device("cuda:0")
-
-    log(f"[bench] workload={args.workload} N={N} K={K} R={R} C={C} B={B}")
-    t = time.perf_counter()
-    raw = synth.db_bytes(args.seed, R, C, N)
-    log(f"[bench] database generated in {time.perf_counter() - t:.1f} s")
-    ctx = pir.Context(0)
-    t = time.perf_counter()
-    db = ctx.load_db(params, raw, R, C)
-    load_s = time.perf_counter() - t
-    del raw
-    log(f"[bench] database loaded (lift+NTT+tiling) in {load_s:.2f} s")
+    db, primes, load_s = load_db(pir, ctx, log2n, K, R, C, args.seed, parallel=False)
     qc = torch.empty((B, R, 2, K, N), dtype=torch.int32, device=dev)
     for b in range(B):
         qc[b] = torch.from_numpy(synth.uniform_query(args.seed, b, R, primes, N).view(np.int32)).to(dev)
@@ -582,32 +830,11 @@ def main() -> int:
     if not args.no_tune:
         tune_report = ctx.tune(db, B)
         log(f"[bench] tuned scan: {tune_report}")
-
-    for _ in range(args.warmup):
-        ctx.answer_batch(jobs)
-    torch.cuda.synchronize()
-    # the scan launches record their own start/end events: no marker commands
-    # between the kernels of the timed steps
-    ctx.profile(True, stages=("scan",))
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for _ in range(args.steps):
-        ctx.answer_batch(jobs)
-    torch.cuda.synchronize()
-    t1 = time.perf_counter()
-    scan_ms, scan_n = ctx.profile_read("scan")
-    # per-stage breakdown from a separate pass with every stage timed
-    ctx.profile(True)
-    for _ in range(max(1, min(args.steps, 10))):
-        ctx.answer_batch(jobs)
-    stage = {s: ctx.profile_read(s) for s in ("ntt", "pack", "scan", "unpack", "intt")}
-    ctx.profile(False)
-    wall = t1 - t0
+    wall, scan_avg_ms, stage = time_steps(ctx, jobs, args.steps, args.warmup)
     ms_per_step = wall * 1e3 / args.steps
     raw_bytes = R * C * N
     value = raw_bytes * B * args.steps / wall / 1e9
-    log(f"[bench] timed {args.steps} steps: {ms_per_step:.4f} ms/step")
-
+    log(f"[bench] {name}: timed {args.steps} steps: {ms_per_step:.4f} ms/step")
     lat = []
     for _ in range(args.latency_steps):
         a = time.perf_counter()
@@ -615,11 +842,11 @@ def main() -> int:
         torch.cuda.synchronize()
         lat.append((time.perf_counter() - a) * 1e3)
     lat = np.array(lat if lat else [float("nan")])
-
-    scan_avg_ms = scan_ms / max(scan_n, 1)
-    alg = scan_alg_bytes(log2n, K, R, C, B)
-    achieved = alg / (scan_avg_ms * 1e-3) / 1e9
     kernel = ctx.scan_kernel(db, B)
+    roof = (hbm_roofline(kernel, log2n, K, R, C, B, scan_avg_ms, measured_traffic(kernel, name))
+            if B == 1 else
+            mfma_roofline(kernel, log2n, K, R, C, B, scan_avg_ms, measured_traffic(kernel, name),
+                          measured_mfma(kernel, name)))
     out = {
         "metric": METRIC,
         "value": round(value, 3),
@@ -648,28 +875,72 @@ def main() -> int:
         "latency_ms": {"p50": round(float(np.percentile(lat, 50)), 4),
                        "p99": round(float(np.percentile(lat, 99)), 4),
                        "what": "one pir_answer_batch call of B queries, host clock, synchronized"},
-        "stage_ms": {s: round(v[0] / max(v[1], 1), 5) for s, v in stage.items()},
+        "stage_ms": stage,
         "stage_ms_what": "a separate pass after the timed steps with every stage bracketed by events",
         "scan_tuning": tune_report,
-        "roofline": {
-            "bound": "hbm",
-            "kernel": kernel,
-            "achieved": round(achieved, 2),
-            "peak": HBM_PEAK_GBS,
-            "unit": "GB/s",
-            "frac": round(achieved / HBM_PEAK_GBS, 4),
-            "traffic": measured_traffic(kernel, args.workload),
-            "alg_bytes_per_launch": alg,
-            "avg_launch_ms": round(scan_avg_ms, 5),
-        },
+        "roofline": roof,
     }
-    if cpu is not None:
-        if [int(x) for x in primes] != [int(x) for x in op.ntt_primes(N, K)]:
-            raise RuntimeError("the oracle's primes differ from the library's")
-        out["cpu_baseline"] = cpu
-    print(json.dumps(out), flush=True)
     db.free()
-    ctx.close()
+    return out
+
+
+def main() -> int:
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--workload", default="headline",
+                    choices=["headline"] + sorted(WORKLOADS) + ["serving", "multidb", "drain",
+                                                                "scalar", "pack"])
+    ap.add_argument("--serve-seconds", type=float, default=3.0)
+    ap.add_argument("--serve-max-requests", type=int, default=1500)
+    ap.add_argument("--seed", type=int, default=0)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--latency-steps", type=int, default=50)
+    ap.add_argument("--no-tune", action="store_true", help="use the default scan variant")
+    ap.add_argument("--no-serving", action="store_true",
+                    help="headline without the serving runs (for short profiled runs)")
+    ap.add_argument("--switch-bits", type=int, default=0,
+                    help="drain the answers with modulus switching to 2^bits (0: plain INTT)")
+    ap.add_argument("--calibrate-copy", action="store_true",
+                    help="only run a plain 1 GiB device copy (for HBM counter scaling)")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(json.dumps({"error": "bench.py measures one GPU only; run it with --gpus 1"}))
+        return 2
+    if args.calibrate_copy:
+        calibrate_copy()
+        return 0
+    if args.workload in ("serving", "multidb", "drain", "scalar", "pack"):
+        fn = {"serving": serve, "multidb": multidb, "drain": drain, "scalar": scalar,
+              "pack": pack}[args.workload]
+        print(json.dumps(fn(args)), flush=True)
+        return 0
+
+    if args.workload == "headline":
+        log2n, K, R, C = (HEADLINE[k] for k in ("log2n", "K", "R", "C"))
+    else:
+        log2n, K, R, C, _ = WORKLOADS[args.workload]
+    cpu = None
+    if not args.no_cpu_baseline:
+        # before anything touches the GPU: the all-core leg forks worker processes
+        from oracle import params as op
+        log("[bench] timing the CPU oracle on a bounded sample")
+        oracle_primes = op.ntt_primes(1 << log2n, K)
+        cpu = cpu_baseline(log2n, K, R, C, oracle_primes, args.seed)
+
+    from paper_2606_11536_amd import pir
+    if cpu is not None and pir.find_primes(log2n, K, 28) != [int(x) for x in oracle_primes]:
+        raise RuntimeError("the oracle's primes differ from the library's")
+    if args.workload == "headline":
+        out = headline(args, cpu)
+    else:
+        ctx = pir.Context(0)
+        out = scan_workload(pir, ctx, args.workload, args)
+        ctx.close()
+        if cpu is not None:
+            out["cpu_baseline"] = cpu
+    print(json.dumps(out), flush=True)
     return 0
 
 

@@ -70,7 +70,8 @@ typedef struct pir_db pir_db;   /* device-resident NTT-form database */
 /* RNS parameters (Sec. 2.3; prime rule of App. A, "RNS prime selection").
  * N = 2^log2_n with 10 <= log2_n <= 12; 1 <= n_primes <= 4; each primes[k]
  * prime, < 2^28, = 1 (mod 2N), all distinct; p = 2^plain_log2 with
- * 1 <= plain_log2 <= 8 (database bytes are plaintext coefficients). */
+ * 1 <= plain_log2 <= 32 (database bytes are plaintext coefficients and are
+ * lifted as they are; ring packing scales by Delta = floor(Q / p)). */
 typedef struct {
   uint32_t log2_n;
   uint32_t n_primes;
@@ -193,6 +194,7 @@ pir_status pir_sdb_mul(pir_ctx *ctx, const pir_sdb *db, const uint32_t *query, u
                        uint32_t *out, pir_stream stream);
 void pir_sdb_free(pir_sdb *db);
 
+
 /* ---- the scan in NTT form (Sec. 3.2 step 6; Sec. 4 INT32 modular GEMM).
  * query_ntt: device [B][R][2][K][N], NTT form; answer_ntt: device
  * [B][C][2][K][N], NTT form, fully overwritten:
@@ -224,6 +226,38 @@ typedef struct {
 
 pir_status pir_answer_batch(pir_ctx *ctx, const pir_job *jobs, size_t n_jobs,
                             pir_stream stream);
+
+/* ---- ring packing of LWE ciphertexts into RLWE ciphertexts (App. C.1,
+ * Eq. tiptoe-rp; Sec. 3.5 "Massive parallelism": H C + (0 | G) as
+ * (#RNS N)-parallel ceil(D1/N) x 2B x n modular GEMMs over NTT-form
+ * polynomials).  The LWE ciphertexts of a client are the rows of (A, b):
+ * A is D1 x n over Z_p (the same for every client: SimplePIR's hint), b its
+ * D1 offsets, p = 2^params->plain_log2.  Cut into C' = ceil(D1/N) chunks of
+ * N rows, chunk r packs into one RLWE ciphertext
+ *     (0, Delta iota(b_r)) + sum_{i<n} iota(A_{r,i}) ct_i      in R_Q^2,
+ * iota(v) = sum_j v_j X^j, A_{r,i}[j] = A[r N + j][i] (zero past D1),
+ * Delta = floor(Q / p), values of Z_p lifted unsigned, ct_i the client's
+ * special ciphertext encrypting its LWE secret entry s_i; it decrypts to
+ * iota(b_r + A_r s) mod p.
+ * pir_pack_load: the offline transform of A ([D1][n] uint32, row-major, each
+ * entry < 2^32; host or device per a_is_device) into an opaque hint H held
+ * like a database of n rows and C' columns (pir_db_info reports R = n,
+ * C = C'); 1 <= n <= PIR_MAX_R, C' <= PIR_MAX_C.  Uses about 2 x D1 n 4
+ * bytes of temporary device memory; synchronizes `stream`; release H with
+ * pir_db_free.  Errors: INVALID_ARG, UNSUPPORTED, BUDGET, OUT_OF_MEMORY,
+ * DEVICE.
+ * pir_pack: for B clients (1 <= B <= PIR_MAX_BATCH), special_coeff device
+ * [B][n][2][K][N] (coefficient form, residues < q_k, left unchanged), lwe_b
+ * device [B][D1] uint32 (< 2^32), out device [B][C'][2][K][N] coefficient
+ * form, or with switch_bits in [1, 32] (K <= 2) the fused modulus switch of
+ * pir_intt_modswitch into [B][C'][2][N] words.  Asynchronous on `stream`;
+ * uses context workspace as pir_answer_batch does for one job, plus
+ * B C' K N 4 bytes for NTT(Delta iota(b)).  INVALID_ARG for a database that
+ * was not loaded by pir_pack_load. */
+pir_status pir_pack_load(pir_ctx *ctx, const pir_params *params, const uint32_t *A, int a_is_device,
+                         uint32_t D1, uint32_t n, pir_stream stream, pir_db **out);
+pir_status pir_pack(pir_ctx *ctx, const pir_db *H, uint32_t B, const uint32_t *special_coeff,
+                    const uint32_t *lwe_b, uint32_t *out, uint32_t switch_bits, pir_stream stream);
 
 /* ---- batch steady state: a job list captured once into a HIP graph.
  * pir_plan_create records what pir_answer_batch(jobs) enqueues (all kernel

@@ -115,8 +115,8 @@ pir_status check_params(pir_ctx *ctx, const pir_params *p) {
   if (p->n_primes < 1 || p->n_primes > PIR_MAX_PRIMES)
     return fail(ctx, PIR_ERR_UNSUPPORTED, "n_primes=%u outside [1, %d]", p->n_primes,
                 PIR_MAX_PRIMES);
-  if (p->plain_log2 < 1 || p->plain_log2 > 8)
-    return fail(ctx, PIR_ERR_UNSUPPORTED, "plain_log2=%u outside [1, 8]", p->plain_log2);
+  if (p->plain_log2 < 1 || p->plain_log2 > 32)
+    return fail(ctx, PIR_ERR_UNSUPPORTED, "plain_log2=%u outside [1, 32]", p->plain_log2);
   const uint64_t twoN = 2ull << p->log2_n;
   for (uint32_t k = 0; k < p->n_primes; ++k) {
     const uint32_t q = p->primes[k];
@@ -514,25 +514,24 @@ pir_status pir_ctx_reserve(pir_ctx *ctx, size_t bytes) {
   return ensure_ws(ctx, bytes);
 }
 
-pir_status pir_db_load_ntt(pir_ctx *ctx, const pir_params *params, const uint8_t *raw,
-                           int raw_is_device, uint32_t R, uint32_t C, pir_stream stream,
-                           pir_db **out) {
-  if (!ctx || !out) return PIR_ERR_INVALID_ARG;
-  *out = nullptr;
-  pir_status st = check_params(ctx, params);
-  if (st != PIR_OK) return st;
-  if (!raw) return fail(ctx, PIR_ERR_INVALID_ARG, "raw is NULL");
-  if (R < 1 || R > PIR_MAX_R || C < 1 || C > PIR_MAX_C)
-    return fail(ctx, PIR_ERR_INVALID_ARG, "R=%u or C=%u out of range", R, C);
-  DeviceGuard g(ctx->device);
-  hipStream_t s = (hipStream_t)stream;
-  const DevPrime *primes = nullptr;
-  if ((st = prime_set(ctx, params, &primes)) != PIR_OK) return st;
+}  // extern "C"
 
+namespace {
+
+// Lift, transform and tile R x C polynomials into a new database.
+// lift(i0, valid, S, tmp) launches the lift + NTT of slab rows [i0, i0 + S)
+// (rows >= i0 + valid zero) into tmp ([K][S][C][N]); after each slab the
+// rows are packed into the scan atoms.
+template <typename Lift>
+pir_status load_rows(pir_ctx *ctx, const pir_params *params, uint32_t R, uint32_t C, hipStream_t s,
+                     Lift lift, pir_db **out) {
+  const DevPrime *primes = nullptr;
+  pir_status st = prime_set(ctx, params, &primes);
+  if (st != PIR_OK) return st;
   const uint32_t N = 1u << params->log2_n, K = params->n_primes;
   const uint32_t Rp = r_pad(R), Cp = c_pad(C);
-  // + a 64 KiB tail: the batched kernel's padded contraction steps read past
-  // the last atom of the last slot (their products meet zero query atoms)
+  // + a tail: the batched kernel's padded contraction steps read past the
+  // last atom of the last slot (their products meet zero query atoms)
   const size_t bytes = (size_t)K * N * Rp * Cp * 4 + kDbTailBytes;
   pir_db *db = new (std::nothrow) pir_db;
   if (!db) return fail(ctx, PIR_ERR_OUT_OF_MEMORY, "host allocation failed");
@@ -550,12 +549,10 @@ pir_status pir_db_load_ntt(pir_ctx *ctx, const pir_params *params, const uint8_t
   uint32_t S = (uint32_t)std::max<size_t>(32, ((256u << 20) / row_bytes) / 32 * 32);
   S = std::min(S, Rp);
   uint32_t *tmp = nullptr;
-  uint8_t *stage = nullptr;
-  const size_t tmp_bytes = (size_t)S * row_bytes, stage_bytes = (size_t)S * C * N;
+  const size_t tmp_bytes = (size_t)S * row_bytes;
   auto cleanup = [&](pir_status code) {
     (void)hipStreamSynchronize(s);
     dev_free(ctx, tmp, tmp_bytes);
-    dev_free(ctx, stage, stage_bytes);
     if (code != PIR_OK) {
       dev_free(ctx, db->atoms, db->bytes);
       delete db;
@@ -563,21 +560,10 @@ pir_status pir_db_load_ntt(pir_ctx *ctx, const pir_params *params, const uint8_t
     return code;
   };
   if ((st = dev_alloc(ctx, (void **)&tmp, tmp_bytes, "load slab")) != PIR_OK) return cleanup(st);
-  if (!raw_is_device &&
-      (st = dev_alloc(ctx, (void **)&stage, stage_bytes, "load staging")) != PIR_OK)
-    return cleanup(st);
   for (uint32_t i0 = 0; i0 < Rp; i0 += S) {
     const uint32_t valid = i0 < R ? std::min(S, R - i0) : 0;
-    const uint8_t *src = raw + (size_t)i0 * C * N;
-    if (!raw_is_device) {
-      if (valid && hipMemcpyAsync(stage, src, (size_t)valid * C * N, hipMemcpyHostToDevice, s) !=
-                       hipSuccess)
-        return cleanup(fail(ctx, PIR_ERR_DEVICE, "host-to-device copy of the raw DB failed"));
-      src = stage;
-    }
-    hipError_t e = launch_lift_ntt(valid ? src : nullptr, tmp, S, valid, C, K, params->log2_n,
-                                   primes, s);
-    if (e == hipSuccess) e = launch_pack_db(tmp, db->atoms, i0, S, R, C, N, K, s);
+    if ((st = lift(i0, valid, S, tmp, primes)) != PIR_OK) return cleanup(st);
+    const hipError_t e = launch_pack_db(tmp, db->atoms, i0, S, R, C, N, K, s);
     if (e != hipSuccess)
       return cleanup(fail(ctx, PIR_ERR_DEVICE, "DB transform launch failed: %s", hipGetErrorString(e)));
   }
@@ -595,6 +581,99 @@ pir_status pir_db_load_ntt(pir_ctx *ctx, const pir_params *params, const uint8_t
   d.n_ib = Rp / kIB;
   *out = db;
   return cleanup(PIR_OK);
+}
+
+}  // namespace
+
+extern "C" {
+
+pir_status pir_db_load_ntt(pir_ctx *ctx, const pir_params *params, const uint8_t *raw,
+                           int raw_is_device, uint32_t R, uint32_t C, pir_stream stream,
+                           pir_db **out) {
+  if (!ctx || !out) return PIR_ERR_INVALID_ARG;
+  *out = nullptr;
+  pir_status st = check_params(ctx, params);
+  if (st != PIR_OK) return st;
+  if (!raw) return fail(ctx, PIR_ERR_INVALID_ARG, "raw is NULL");
+  if (R < 1 || R > PIR_MAX_R || C < 1 || C > PIR_MAX_C)
+    return fail(ctx, PIR_ERR_INVALID_ARG, "R=%u or C=%u out of range", R, C);
+  DeviceGuard g(ctx->device);
+  hipStream_t s = (hipStream_t)stream;
+  const uint32_t N = 1u << params->log2_n, K = params->n_primes;
+  uint8_t *stage = nullptr;
+  size_t stage_bytes = 0;
+  if (!raw_is_device) {
+    const size_t row_bytes = (size_t)K * C * N * 4;
+    const uint32_t S = std::min((uint32_t)std::max<size_t>(32, ((256u << 20) / row_bytes) / 32 * 32),
+                                r_pad(R));
+    stage_bytes = (size_t)S * C * N;
+    if ((st = dev_alloc(ctx, (void **)&stage, stage_bytes, "load staging")) != PIR_OK) return st;
+  }
+  auto lift = [&](uint32_t i0, uint32_t valid, uint32_t S, uint32_t *tmp, const DevPrime *primes) {
+    const uint8_t *src = raw + (size_t)i0 * C * N;
+    if (!raw_is_device && valid) {
+      if (S * (size_t)C * N > stage_bytes ||
+          hipMemcpyAsync(stage, src, (size_t)valid * C * N, hipMemcpyHostToDevice, s) != hipSuccess)
+        return fail(ctx, PIR_ERR_DEVICE, "host-to-device copy of the raw DB failed");
+      src = stage;
+    }
+    const hipError_t e = launch_lift_ntt(valid ? src : nullptr, tmp, S, valid, C, K,
+                                         params->log2_n, primes, s);
+    return e == hipSuccess ? PIR_OK
+                           : fail(ctx, PIR_ERR_DEVICE, "DB transform launch failed: %s",
+                                  hipGetErrorString(e));
+  };
+  st = load_rows(ctx, params, R, C, s, lift, out);
+  (void)hipStreamSynchronize(s);
+  dev_free(ctx, stage, stage_bytes);
+  return st;
+}
+
+pir_status pir_pack_load(pir_ctx *ctx, const pir_params *params, const uint32_t *A, int a_is_device,
+                         uint32_t D1, uint32_t n, pir_stream stream, pir_db **out) {
+  if (!ctx || !out) return PIR_ERR_INVALID_ARG;
+  *out = nullptr;
+  pir_status st = check_params(ctx, params);
+  if (st != PIR_OK) return st;
+  if (!A) return fail(ctx, PIR_ERR_INVALID_ARG, "A is NULL");
+  const uint32_t N = 1u << params->log2_n;
+  const uint32_t Cp = (uint32_t)(((uint64_t)D1 + N - 1) / N);
+  if (D1 < 1 || n < 1 || n > PIR_MAX_R || Cp > PIR_MAX_C)
+    return fail(ctx, PIR_ERR_INVALID_ARG, "D1=%u or n=%u out of range", D1, n);
+  DeviceGuard g(ctx->device);
+  hipStream_t s = (hipStream_t)stream;
+  const size_t a_bytes = (size_t)D1 * n * 4, at_bytes = (size_t)n * Cp * N * 4;
+  uint32_t *a_dev = nullptr, *at = nullptr;
+  auto done = [&](pir_status code) {
+    (void)hipStreamSynchronize(s);
+    if (!a_is_device) dev_free(ctx, a_dev, a_bytes);
+    dev_free(ctx, at, at_bytes);
+    return code;
+  };
+  if (a_is_device) {
+    a_dev = const_cast<uint32_t *>(A);
+  } else {
+    if ((st = dev_alloc(ctx, (void **)&a_dev, a_bytes, "LWE matrix staging")) != PIR_OK)
+      return done(st);
+    if (hipMemcpyAsync(a_dev, A, a_bytes, hipMemcpyHostToDevice, s) != hipSuccess)
+      return done(fail(ctx, PIR_ERR_DEVICE, "host-to-device copy of the LWE matrix failed"));
+  }
+  // A [D1][n] -> AT [n][Cp N]: row i of AT holds column i of A, so that
+  // polynomial (i, r) (coefficient j = A[r N + j][i]) is AT[i][r N .. r N + N)
+  if ((st = dev_alloc(ctx, (void **)&at, at_bytes, "LWE matrix transpose")) != PIR_OK)
+    return done(st);
+  if (launch_transpose32(a_dev, at, D1, n, Cp * N, s) != hipSuccess)
+    return done(fail(ctx, PIR_ERR_DEVICE, "transpose launch failed"));
+  auto lift = [&](uint32_t i0, uint32_t valid, uint32_t S, uint32_t *tmp, const DevPrime *primes) {
+    const hipError_t e = launch_lift_ntt32(valid ? at + (size_t)i0 * Cp * N : nullptr, tmp, S, valid,
+                                           Cp, params->n_primes, params->log2_n, primes, s);
+    return e == hipSuccess ? PIR_OK
+                           : fail(ctx, PIR_ERR_DEVICE, "hint transform launch failed: %s",
+                                  hipGetErrorString(e));
+  };
+  st = load_rows(ctx, params, n, Cp, s, lift, out);
+  if (st == PIR_OK) (*out)->pack_d1 = D1;
+  return done(st);
 }
 
 pir_status pir_db_info(const pir_db *db, pir_params *params, uint32_t *R, uint32_t *C,
@@ -798,8 +877,10 @@ namespace {
 
 // Enqueue the whole batch (NTT, packing, fused scans, INTT) on `s` using the
 // workspace at `ws` (at least p.bytes()).
+// add (may be null): per job, an addend for the component-1 answer
+// polynomials ([B][C][K][N], NTT form) taken in by the drain (ring packing).
 pir_status enqueue_batch(pir_ctx *ctx, const pir_job *jobs, size_t n_jobs, uint8_t *ws,
-                         BatchPlan &p, hipStream_t s) {
+                         BatchPlan &p, hipStream_t s, const uint32_t *const *add = nullptr) {
   place_batch(jobs, n_jobs, ws, p);
   for (size_t n = 0; n < n_jobs; ++n) {
     const pir_job &j = jobs[n];
@@ -829,14 +910,15 @@ pir_status enqueue_batch(pir_ctx *ctx, const pir_job *jobs, size_t n_jobs, uint8
       HIP_OR_FAIL(ctx, launch_unpack_answers(p.sm[n], P, 0, P, d.K * d.N, p.ans[n], s));
     }
     StageTimer tm(ctx, s, PIR_STAGE_INTT);
+    const uint32_t *a = add ? add[n] : nullptr;
     if (jobs[n].switch_bits) {
       HIP_OR_FAIL(ctx, launch_intt_switch(p.ans[n], jobs[n].answer_coeff,
                                           (size_t)jobs[n].B * d.C * 2, d.K,
                                           jobs[n].db->params.primes, d.log2n, d.primes,
-                                          jobs[n].switch_bits, s));
+                                          jobs[n].switch_bits, s, a));
     } else {
       HIP_OR_FAIL(ctx, launch_ntt(jobs[n].answer_coeff, (size_t)jobs[n].B * d.C * 2 * d.K, d.K,
-                                  d.log2n, d.primes, true, s));
+                                  d.log2n, d.primes, true, s, a));
     }
   }
   return PIR_OK;
@@ -866,6 +948,37 @@ pir_status pir_answer_batch(pir_ctx *ctx, const pir_job *jobs, size_t n_jobs, pi
   DeviceGuard g(ctx->device);
   if ((st = ensure_ws(ctx, p.bytes())) != PIR_OK) return st;
   return enqueue_batch(ctx, jobs, n_jobs, (uint8_t *)ctx->ws, p, (hipStream_t)stream);
+}
+
+pir_status pir_pack(pir_ctx *ctx, const pir_db *H, uint32_t B, const uint32_t *special_coeff,
+                    const uint32_t *lwe_b, uint32_t *out, uint32_t switch_bits, pir_stream stream) {
+  if (!ctx) return PIR_ERR_INVALID_ARG;
+  if (!H || !special_coeff || !lwe_b || !out) return fail(ctx, PIR_ERR_INVALID_ARG, "null argument");
+  if (H->ctx != ctx) return fail(ctx, PIR_ERR_INVALID_ARG, "hint belongs to another context");
+  if (!H->pack_d1) return fail(ctx, PIR_ERR_INVALID_ARG, "not a ring-packing hint (pir_pack_load)");
+  const pir_job job{H, B, special_coeff, out, switch_bits};
+  BatchPlan p;
+  pir_status st = plan_batch(ctx, &job, 1, p);   // checks B and switch_bits
+  if (st != PIR_OK) return st;
+  const DbDesc &d = H->desc;
+  // Delta = floor(Q / p) mod q_k, Q = prod q_k < 2^112
+  unsigned __int128 Q = 1;
+  for (uint32_t k = 0; k < d.K; ++k) Q *= H->params.primes[k];
+  const unsigned __int128 delta = Q >> H->params.plain_log2;
+  uint32_t dk[PIR_MAX_PRIMES] = {};
+  for (uint32_t k = 0; k < d.K; ++k) dk[k] = (uint32_t)(delta % H->params.primes[k]);
+  DeviceGuard g(ctx->device);
+  const size_t g_bytes = al256((size_t)B * d.C * d.K * d.N * 4);
+  if ((st = ensure_ws(ctx, p.bytes() + g_bytes)) != PIR_OK) return st;
+  hipStream_t s = (hipStream_t)stream;
+  uint32_t *gmat = (uint32_t *)((uint8_t *)ctx->ws + p.bytes());
+  {
+    StageTimer tm(ctx, s, PIR_STAGE_NTT);
+    HIP_OR_FAIL(ctx, launch_offset_ntt(lwe_b, gmat, B, H->pack_d1, d.C, d.K, d.log2n, d.primes, dk,
+                                       s));
+  }
+  const uint32_t *add[1] = {gmat};
+  return enqueue_batch(ctx, &job, 1, (uint8_t *)ctx->ws, p, s, add);
 }
 
 pir_status pir_plan_create(pir_ctx *ctx, const pir_job *jobs, size_t n_jobs, pir_stream stream,

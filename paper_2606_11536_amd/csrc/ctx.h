@@ -48,6 +48,7 @@ struct pir_db {
   pir_ctx *ctx = nullptr;
   pir_params params{};
   uint32_t R = 0, C = 0;
+  uint32_t pack_d1 = 0;  // ring-packing hint: rows D1 of the LWE matrix (0: a database)
   size_t bytes = 0;
   uint8_t *atoms = nullptr;
   pir::DbDesc desc{};

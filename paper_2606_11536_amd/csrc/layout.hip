@@ -204,6 +204,27 @@ __global__ __launch_bounds__(256) void k_unpack_answers(const uint32_t *__restri
   }
 }
 
+// in [rows][cols] -> out [cols][out_rows], zeros in columns rows .. out_rows - 1
+// of out.  64 x 64 tiles through LDS, 256-byte rows on both sides.
+__global__ __launch_bounds__(256) void k_transpose32(const uint32_t *__restrict__ in,
+                                                     uint32_t *__restrict__ out, uint32_t rows,
+                                                     uint32_t cols, uint32_t out_rows) {
+  __shared__ uint32_t tile[64][65];
+  const uint32_t r0 = blockIdx.x * 64, c0 = blockIdx.y * 64;
+  const uint32_t tx = threadIdx.x & 63, ty = threadIdx.x >> 6;
+#pragma unroll
+  for (uint32_t k = 0; k < 16; ++k) {
+    const uint32_t r = r0 + ty + 4 * k, c = c0 + tx;
+    tile[ty + 4 * k][tx] = r < rows && c < cols ? in[(size_t)r * cols + c] : 0u;
+  }
+  __syncthreads();
+#pragma unroll
+  for (uint32_t k = 0; k < 16; ++k) {
+    const uint32_t c = c0 + ty + 4 * k, r = r0 + tx;
+    if (c < cols && r < out_rows) out[(size_t)c * out_rows + r] = tile[tx][ty + 4 * k];
+  }
+}
+
 // Timing data for the autotuner: word i = hash(i) & 0x0F7F7F7F (every byte a
 // valid 7-bit limb, every word below 2^28).  Timing depends on the data: the
 // matrix cores draw more power on random operands than on zeros.
@@ -226,6 +247,14 @@ hipError_t launch_fill_tuning(uint32_t *p, size_t n_words, hipStream_t s) {
   if (n_words == 0) return hipSuccess;
   const size_t blocks = std::min<size_t>((n_words + 255) / 256, 65536);
   k_fill_tuning<<<(unsigned)blocks, 256, 0, s>>>(p, n_words);
+  return hipGetLastError();
+}
+
+hipError_t launch_transpose32(const uint32_t *in, uint32_t *out, uint32_t rows, uint32_t cols,
+                              uint32_t out_rows, hipStream_t s) {
+  if (out_rows < rows || cols == 0 || out_rows == 0) return hipErrorInvalidValue;
+  k_transpose32<<<dim3((out_rows + 63) / 64, (cols + 63) / 64), 256, 0, s>>>(in, out, rows, cols,
+                                                                             out_rows);
   return hipGetLastError();
 }
 

@@ -124,25 +124,36 @@ __device__ __forceinline__ void rounds_from(double (&x)[Geo<LOGN>::E], uint32_t 
 }
 
 // Transform x (exact integers, loaded with round-0 indexing); on return out
-// holds canonical residues in [0, q) laid out with last-round indexing.
+// holds canonical residues in [0, q) laid out with last-round indexing.  The
+// inverse multiplies by N^-1; a forward transform with scale != 0 multiplies
+// every output by scale (mod q), which by linearity is the transform of the
+// scaled input.  Inputs may be any integers of magnitude below 2^33 (forward)
+// or 2^29 (inverse): the stage bounds above then still hold.
 template <int LOGN, bool INV>
 __device__ __forceinline__ void transform(double (&x)[Geo<LOGN>::E],
                                           uint32_t (&out)[Geo<LOGN>::E], uint32_t tid,
-                                          double *sm, const DevPrime &P) {
+                                          double *sm, const DevPrime &P, uint32_t scale = 0) {
   constexpr int N = Geo<LOGN>::N;
   const double q = (double)P.q, inv_q = 1.0 / q;
   const uint32_t *tw = P.tw + (INV ? 2 * N : 0);
   rounds_from<LOGN, INV, 0>(x, tid, sm, tw, q, inv_q);
-  const double ninv = (double)P.ninv;
+  const double f = INV ? (double)P.ninv : (double)scale;
+  const bool mul = INV || scale != 0;
 #pragma unroll
   for (int e = 0; e < Geo<LOGN>::E; ++e)
-    out[e] = reduce_f64(INV ? mulmod_f64(x[e], ninv, q, inv_q) : x[e], q, inv_q);
+    out[e] = reduce_f64(mul ? mulmod_f64(x[e], f, q, inv_q) : x[e], q, inv_q);
 }
 
-template <int LOGN, bool INV>
+// One residue row per block.  With an addend (inverse only): the rows are
+// answer ciphertexts [..][2][K][N], and every row of a component-1 polynomial
+// (p = row / K odd) first gets row (p / 2) K + row % K of `add` added -- the
+// (0 | G) term of ring packing, added before the inverse transform (which is
+// linear), so that no separate pass over the answers is needed.
+template <int LOGN, bool INV, bool ADD>
 __global__ __launch_bounds__(kThreads) void k_ntt_rows(const uint32_t *__restrict__ src,
                                                        uint32_t *__restrict__ dst, uint32_t K,
-                                                       const DevPrime *__restrict__ primes) {
+                                                       const DevPrime *__restrict__ primes,
+                                                       const uint32_t *__restrict__ add) {
   using G = Geo<LOGN>;
   __shared__ double sm[G::N];
   const uint32_t tid = threadIdx.x;
@@ -153,6 +164,14 @@ __global__ __launch_bounds__(kThreads) void k_ntt_rows(const uint32_t *__restric
   double x[G::E];
 #pragma unroll
   for (int e = 0; e < G::E; ++e) x[e] = (double)in[ridx<LOGN, INV, 0>(tid, e)];
+  if constexpr (ADD) {
+    const size_t p = row / K;
+    if (p & 1) {
+      const uint32_t *a = add + ((p >> 1) * K + row % K) * G::N;
+#pragma unroll
+      for (int e = 0; e < G::E; ++e) x[e] += (double)a[ridx<LOGN, INV, 0>(tid, e)];
+    }
+  }
   uint32_t y[G::E];
   transform<LOGN, INV>(x, y, tid, sm, P);
   constexpr int LAST = G::ROUNDS - 1;
@@ -160,9 +179,11 @@ __global__ __launch_bounds__(kThreads) void k_ntt_rows(const uint32_t *__restric
   for (int e = 0; e < G::E; ++e) out[ridx<LOGN, INV, LAST>(tid, e)] = y[e];
 }
 
-// raw: [rows][N] uint8 (rows = S*C of the slab); out: [K][rows][N].
-template <int LOGN>
-__global__ __launch_bounds__(kThreads) void k_lift_ntt(const uint8_t *__restrict__ raw,
+// raw: [rows][N] uint8 or uint32 (rows = S*C of the slab); out: [K][rows][N].
+// The unsigned lift: a coefficient v < 2^32 is the integer v, reduced mod q_k
+// by the transform's final reduction.
+template <int LOGN, typename T>
+__global__ __launch_bounds__(kThreads) void k_lift_ntt(const T *__restrict__ raw,
                                                        uint32_t *__restrict__ out, uint32_t rows,
                                                        uint32_t valid_rows,
                                                        const DevPrime *__restrict__ primes) {
@@ -174,7 +195,7 @@ __global__ __launch_bounds__(kThreads) void k_lift_ntt(const uint8_t *__restrict
   const DevPrime &P = primes[k];
   double x[G::E];
   if (row < valid_rows) {
-    const uint8_t *in = raw + (size_t)row * G::N;
+    const T *in = raw + (size_t)row * G::N;
 #pragma unroll
     for (int e = 0; e < G::E; ++e) x[e] = (double)in[ridx<LOGN, false, 0>(tid, e)];
   } else {
@@ -184,6 +205,41 @@ __global__ __launch_bounds__(kThreads) void k_lift_ntt(const uint8_t *__restrict
   uint32_t y[G::E];
   transform<LOGN, false>(x, y, tid, sm, P);
   uint32_t *o = out + ((size_t)k * rows + row) * G::N;
+  constexpr int LAST = G::ROUNDS - 1;
+#pragma unroll
+  for (int e = 0; e < G::E; ++e) o[ridx<LOGN, false, LAST>(tid, e)] = y[e];
+}
+
+// The (0 | G) term of ring packing: G = NTT(Delta iota(b)) for every client
+// beta and chunk r of its offsets b[beta][0 .. D1).  Row (beta, r), prime k:
+// coefficient j is b[beta][r N + j] (zero past D1), lifted unsigned; by
+// linearity the transform's output is scaled by Delta mod q_k (delta[k]).
+// out: [B][C'][K][N].
+struct OffsetArgs {
+  uint32_t D1, Cp, K;
+  uint32_t delta[PIR_MAX_PRIMES];
+};
+
+template <int LOGN>
+__global__ __launch_bounds__(kThreads) void k_offset_ntt(const uint32_t *__restrict__ b,
+                                                         uint32_t *__restrict__ out,
+                                                         const DevPrime *__restrict__ primes,
+                                                         const OffsetArgs a) {
+  using G = Geo<LOGN>;
+  __shared__ double sm[G::N];
+  const uint32_t tid = threadIdx.x;
+  const uint32_t row = blockIdx.x, k = blockIdx.y;
+  const uint32_t beta = row / a.Cp, r = row % a.Cp;
+  const uint32_t *in = b + (size_t)beta * a.D1;
+  double x[G::E];
+#pragma unroll
+  for (int e = 0; e < G::E; ++e) {
+    const uint32_t j = r * G::N + ridx<LOGN, false, 0>(tid, e);
+    x[e] = j < a.D1 ? (double)in[j] : 0.0;
+  }
+  uint32_t y[G::E];
+  transform<LOGN, false>(x, y, tid, sm, primes[k], a.delta[k]);
+  uint32_t *o = out + ((size_t)row * a.K + k) * G::N;
   constexpr int LAST = G::ROUNDS - 1;
 #pragma unroll
   for (int e = 0; e < G::E; ++e) o[ridx<LOGN, false, LAST>(tid, e)] = y[e];
@@ -230,16 +286,20 @@ __device__ __forceinline__ uint32_t mod_switch(uint32_t x0, uint32_t x1, const M
 // loaded up front, inverse-transformed one after the other in the same LDS,
 // and every coefficient is switched on its way out: [N] words, no
 // intermediate coefficient form in HBM.
-template <int LOGN, bool TWO>
+// With an addend, odd polynomials (component 1 of [..][2] answers) first get
+// polynomial poly / 2 of `add` ([..][K][N]) added, as in k_ntt_rows.
+template <int LOGN, bool TWO, bool ADD>
 __global__ __launch_bounds__(kThreads) void k_intt_switch(const uint32_t *__restrict__ src,
                                                           uint32_t *__restrict__ dst,
                                                           const DevPrime *__restrict__ primes,
-                                                          const MsArgs m) {
+                                                          const MsArgs m,
+                                                          const uint32_t *__restrict__ add) {
   using G = Geo<LOGN>;
+  constexpr uint32_t KK = TWO ? 2 : 1;
   __shared__ double sm[G::N];
   const uint32_t tid = threadIdx.x;
   const size_t poly = blockIdx.x;
-  const uint32_t *in = src + poly * (TWO ? 2 : 1) * G::N;
+  const uint32_t *in = src + poly * KK * G::N;
   uint32_t u0[G::E], u1[G::E];
 #pragma unroll
   for (int e = 0; e < G::E; ++e) {
@@ -248,13 +308,22 @@ __global__ __launch_bounds__(kThreads) void k_intt_switch(const uint32_t *__rest
   }
   double x[G::E];
   uint32_t y0[G::E], y1[G::E];
+  const uint32_t *a = ADD && (poly & 1) ? add + (poly >> 1) * KK * G::N : nullptr;
 #pragma unroll
   for (int e = 0; e < G::E; ++e) x[e] = (double)u0[e];
+  if (ADD && a) {
+#pragma unroll
+    for (int e = 0; e < G::E; ++e) x[e] += (double)a[ridx<LOGN, true, 0>(tid, e)];
+  }
   transform<LOGN, true>(x, y0, tid, sm, primes[0]);
   if constexpr (TWO) {
     __syncthreads();  // the first transform's last LDS reads are done
 #pragma unroll
     for (int e = 0; e < G::E; ++e) x[e] = (double)u1[e];
+    if (ADD && a) {
+#pragma unroll
+      for (int e = 0; e < G::E; ++e) x[e] += (double)a[G::N + ridx<LOGN, true, 0>(tid, e)];
+    }
     transform<LOGN, true>(x, y1, tid, sm, primes[1]);
   }
   constexpr int LAST = G::ROUNDS - 1;
@@ -264,15 +333,38 @@ __global__ __launch_bounds__(kThreads) void k_intt_switch(const uint32_t *__rest
     out[ridx<LOGN, true, LAST>(tid, e)] = mod_switch<TWO>(y0[e], TWO ? y1[e] : 0u, m);
 }
 
-template <bool INV>
+template <bool INV, bool ADD>
 hipError_t ntt_rows_dispatch(const uint32_t *src, uint32_t *dst, size_t n_rows, uint32_t K,
-                             uint32_t log2n, const DevPrime *primes, hipStream_t s) {
+                             uint32_t log2n, const DevPrime *primes, const uint32_t *add,
+                             hipStream_t s) {
   if (n_rows == 0) return hipSuccess;
   const dim3 grid((unsigned)n_rows), block(kThreads);
   switch (log2n) {
-    case 10: k_ntt_rows<10, INV><<<grid, block, 0, s>>>(src, dst, K, primes); break;
-    case 11: k_ntt_rows<11, INV><<<grid, block, 0, s>>>(src, dst, K, primes); break;
-    case 12: k_ntt_rows<12, INV><<<grid, block, 0, s>>>(src, dst, K, primes); break;
+    case 10: k_ntt_rows<10, INV, ADD><<<grid, block, 0, s>>>(src, dst, K, primes, add); break;
+    case 11: k_ntt_rows<11, INV, ADD><<<grid, block, 0, s>>>(src, dst, K, primes, add); break;
+    case 12: k_ntt_rows<12, INV, ADD><<<grid, block, 0, s>>>(src, dst, K, primes, add); break;
+    default: return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
+template <int LOGN, bool TWO>
+void intt_switch_launch(const uint32_t *src, uint32_t *dst, size_t n_polys, const DevPrime *primes,
+                        const MsArgs &m, const uint32_t *add, hipStream_t s) {
+  const dim3 grid((unsigned)n_polys), block(kThreads);
+  if (add) k_intt_switch<LOGN, TWO, true><<<grid, block, 0, s>>>(src, dst, primes, m, add);
+  else k_intt_switch<LOGN, TWO, false><<<grid, block, 0, s>>>(src, dst, primes, m, nullptr);
+}
+
+template <typename T>
+hipError_t lift_ntt_dispatch(const T *raw, uint32_t *out, uint32_t S, uint32_t s_valid, uint32_t C,
+                             uint32_t K, uint32_t log2n, const DevPrime *primes, hipStream_t s) {
+  const uint32_t rows = S * C, valid = s_valid * C;
+  const dim3 grid(rows, K), block(kThreads);
+  switch (log2n) {
+    case 10: k_lift_ntt<10, T><<<grid, block, 0, s>>>(raw, out, rows, valid, primes); break;
+    case 11: k_lift_ntt<11, T><<<grid, block, 0, s>>>(raw, out, rows, valid, primes); break;
+    case 12: k_lift_ntt<12, T><<<grid, block, 0, s>>>(raw, out, rows, valid, primes); break;
     default: return hipErrorInvalidValue;
   }
   return hipGetLastError();
@@ -281,19 +373,21 @@ hipError_t ntt_rows_dispatch(const uint32_t *src, uint32_t *dst, size_t n_rows, 
 }  // namespace
 
 hipError_t launch_ntt(uint32_t *data, size_t n_rows, uint32_t K, uint32_t log2n,
-                      const DevPrime *primes, bool inverse, hipStream_t s) {
-  return inverse ? ntt_rows_dispatch<true>(data, data, n_rows, K, log2n, primes, s)
-                 : ntt_rows_dispatch<false>(data, data, n_rows, K, log2n, primes, s);
+                      const DevPrime *primes, bool inverse, hipStream_t s, const uint32_t *add) {
+  if (add && !inverse) return hipErrorInvalidValue;
+  if (add) return ntt_rows_dispatch<true, true>(data, data, n_rows, K, log2n, primes, add, s);
+  return inverse ? ntt_rows_dispatch<true, false>(data, data, n_rows, K, log2n, primes, nullptr, s)
+                 : ntt_rows_dispatch<false, false>(data, data, n_rows, K, log2n, primes, nullptr, s);
 }
 
 hipError_t launch_ntt_copy(const uint32_t *src, uint32_t *dst, size_t n_rows, uint32_t K,
                            uint32_t log2n, const DevPrime *primes, hipStream_t s) {
-  return ntt_rows_dispatch<false>(src, dst, n_rows, K, log2n, primes, s);
+  return ntt_rows_dispatch<false, false>(src, dst, n_rows, K, log2n, primes, nullptr, s);
 }
 
 hipError_t launch_intt_switch(const uint32_t *src, uint32_t *dst, size_t n_polys, uint32_t K,
                               const uint32_t *q, uint32_t log2n, const DevPrime *primes,
-                              uint32_t bits, hipStream_t s) {
+                              uint32_t bits, hipStream_t s, const uint32_t *add) {
   if (n_polys == 0) return hipSuccess;
   if (K < 1 || K > 2 || bits < 1 || bits > 32) return hipErrorInvalidValue;
   MsArgs m{};
@@ -312,20 +406,19 @@ hipError_t launch_intt_switch(const uint32_t *src, uint32_t *dst, size_t n_polys
   m.c = (double)(K == 2 ? (uint32_t)((t0 % (int64_t)m.q1 + m.q1) % m.q1) : 0u);
   m.bits = bits;
   m.mask = bits == 32 ? 0xffffffffu : (1u << bits) - 1;
-  const dim3 grid((unsigned)n_polys), block(kThreads);
   const bool two = K == 2;
   switch (log2n) {
     case 10:
-      if (two) k_intt_switch<10, true><<<grid, block, 0, s>>>(src, dst, primes, m);
-      else k_intt_switch<10, false><<<grid, block, 0, s>>>(src, dst, primes, m);
+      if (two) intt_switch_launch<10, true>(src, dst, n_polys, primes, m, add, s);
+      else intt_switch_launch<10, false>(src, dst, n_polys, primes, m, add, s);
       break;
     case 11:
-      if (two) k_intt_switch<11, true><<<grid, block, 0, s>>>(src, dst, primes, m);
-      else k_intt_switch<11, false><<<grid, block, 0, s>>>(src, dst, primes, m);
+      if (two) intt_switch_launch<11, true>(src, dst, n_polys, primes, m, add, s);
+      else intt_switch_launch<11, false>(src, dst, n_polys, primes, m, add, s);
       break;
     case 12:
-      if (two) k_intt_switch<12, true><<<grid, block, 0, s>>>(src, dst, primes, m);
-      else k_intt_switch<12, false><<<grid, block, 0, s>>>(src, dst, primes, m);
+      if (two) intt_switch_launch<12, true>(src, dst, n_polys, primes, m, add, s);
+      else intt_switch_launch<12, false>(src, dst, n_polys, primes, m, add, s);
       break;
     default: return hipErrorInvalidValue;
   }
@@ -335,12 +428,30 @@ hipError_t launch_intt_switch(const uint32_t *src, uint32_t *dst, size_t n_polys
 hipError_t launch_lift_ntt(const uint8_t *raw, uint32_t *out, uint32_t S, uint32_t s_valid,
                            uint32_t C, uint32_t K, uint32_t log2n, const DevPrime *primes,
                            hipStream_t s) {
-  const uint32_t rows = S * C, valid = s_valid * C;
-  const dim3 grid(rows, K), block(kThreads);
+  return lift_ntt_dispatch<uint8_t>(raw, out, S, s_valid, C, K, log2n, primes, s);
+}
+
+hipError_t launch_lift_ntt32(const uint32_t *raw, uint32_t *out, uint32_t S, uint32_t s_valid,
+                             uint32_t C, uint32_t K, uint32_t log2n, const DevPrime *primes,
+                             hipStream_t s) {
+  return lift_ntt_dispatch<uint32_t>(raw, out, S, s_valid, C, K, log2n, primes, s);
+}
+
+hipError_t launch_offset_ntt(const uint32_t *b, uint32_t *out, uint32_t B, uint32_t D1,
+                             uint32_t Cp, uint32_t K, uint32_t log2n, const DevPrime *primes,
+                             const uint32_t *delta, hipStream_t s) {
+  if (B == 0) return hipSuccess;
+  if (K < 1 || K > PIR_MAX_PRIMES) return hipErrorInvalidValue;
+  OffsetArgs a{};
+  a.D1 = D1;
+  a.Cp = Cp;
+  a.K = K;
+  for (uint32_t k = 0; k < K; ++k) a.delta[k] = delta[k];
+  const dim3 grid(B * Cp, K), block(kThreads);
   switch (log2n) {
-    case 10: k_lift_ntt<10><<<grid, block, 0, s>>>(raw, out, rows, valid, primes); break;
-    case 11: k_lift_ntt<11><<<grid, block, 0, s>>>(raw, out, rows, valid, primes); break;
-    case 12: k_lift_ntt<12><<<grid, block, 0, s>>>(raw, out, rows, valid, primes); break;
+    case 10: k_offset_ntt<10><<<grid, block, 0, s>>>(b, out, primes, a); break;
+    case 11: k_offset_ntt<11><<<grid, block, 0, s>>>(b, out, primes, a); break;
+    case 12: k_offset_ntt<12><<<grid, block, 0, s>>>(b, out, primes, a); break;
     default: return hipErrorInvalidValue;
   }
   return hipGetLastError();

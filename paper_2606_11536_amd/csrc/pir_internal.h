@@ -74,14 +74,30 @@ struct DbDesc {
 // Launchers (implemented in the .hip files).  All are asynchronous on `s`.
 // ---------------------------------------------------------------------------
 // In-place forward / inverse NTT of rows [n_rows][N], row r uses prime r % K.
+// add (inverse only, may be null): the rows are answers [..][2][K][N] and
+// rows of component 1 first get the matching row of add ([..][K][N]) added.
 hipError_t launch_ntt(uint32_t *data, size_t n_rows, uint32_t K, uint32_t log2n,
-                      const DevPrime *primes, bool inverse, hipStream_t s);
+                      const DevPrime *primes, bool inverse, hipStream_t s,
+                      const uint32_t *add = nullptr);
 // Out-of-place forward NTT: src and dst both [n_rows][N] (row r -> prime r % K).
 // Fused inverse NTT and modulus switching of n_polys answer polynomials
 // [K][N] (K = 1 or 2, host primes q[K]) into [N] words mod 2^bits each.
 hipError_t launch_intt_switch(const uint32_t *src, uint32_t *dst, size_t n_polys, uint32_t K,
                               const uint32_t *q, uint32_t log2n, const DevPrime *primes,
-                              uint32_t bits, hipStream_t s);
+                              uint32_t bits, hipStream_t s, const uint32_t *add = nullptr);
+// G = NTT(Delta iota(b)) of ring packing: b [B][D1] uint32 cut into Cp chunks
+// of N, out [B][Cp][K][N]; delta[k] = Delta mod q_k.
+hipError_t launch_offset_ntt(const uint32_t *b, uint32_t *out, uint32_t B, uint32_t D1,
+                             uint32_t Cp, uint32_t K, uint32_t log2n, const DevPrime *primes,
+                             const uint32_t *delta, hipStream_t s);
+// Lift + forward NTT of uint32 rows (the ring-packing hint), as launch_lift_ntt.
+hipError_t launch_lift_ntt32(const uint32_t *raw, uint32_t *out, uint32_t S, uint32_t s_valid,
+                             uint32_t C, uint32_t K, uint32_t log2n, const DevPrime *primes,
+                             hipStream_t s);
+// Transpose a [rows][cols] uint32 matrix into out [cols][out_rows] (out_rows
+// >= rows; entries past `rows` are zero).
+hipError_t launch_transpose32(const uint32_t *in, uint32_t *out, uint32_t rows, uint32_t cols,
+                              uint32_t out_rows, hipStream_t s);
 // Scalar-HE database GEMM mod 2^32 (sgemm.hip): database int8 [D1][D0] into
 // atoms [n_rb][n_kb]; queries uint32 [B][D0] into digit atoms [n_kb][n_cb];
 // out [B][D1] = DB Q^T mod 2^32.  n_kb a multiple of 8, n_cb of 4.

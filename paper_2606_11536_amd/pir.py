@@ -65,6 +65,9 @@ SIGNATURES = {
     "pir_sdb_free": (None, [_P]),
     "pir_db_mul": (ct.c_int, [_P, _P, _P, _U32, _P, _P]),
     "pir_answer_batch": (ct.c_int, [_P, ct.POINTER(CJob), ct.c_size_t, _P]),
+    "pir_pack_load": (ct.c_int, [_P, ct.POINTER(CParams), _P, ct.c_int, _U32, _U32, _P,
+                                 ct.POINTER(ct.c_void_p)]),
+    "pir_pack": (ct.c_int, [_P, _P, _U32, _P, _P, _P, _U32, _P]),
     "pir_scan_variants": (ct.c_uint32, [_U32]),
     "pir_scan_select": (ct.c_int, [_P, _P, _U32, _U32]),
     "pir_scan_kernel": (ct.c_char_p, [_P, _P, _U32]),
@@ -276,6 +279,32 @@ class Context:
         db = Database(self, h, params, R, C)
         self._dbs.add(db)
         return db
+
+    def load_pack(self, params: Params, A, D1: int, n: int, stream=None) -> Database:
+        """Offline transform of an LWE matrix A [D1][n] (uint32; numpy array or torch
+        tensor) into a ring-packing hint (pir_pack_load)."""
+        h = ct.c_void_p()
+        if hasattr(A, "data_ptr"):
+            assert A.is_contiguous() and A.numel() == D1 * n and A.element_size() == 4
+            is_dev, ptr = int(A.is_cuda), ct.c_void_p(A.data_ptr())
+        else:
+            import numpy as np
+            A = np.ascontiguousarray(A, dtype=np.uint32)
+            assert A.size == D1 * n
+            is_dev, ptr = 0, A.ctypes.data_as(ct.c_void_p)
+        _check(lib.pir_pack_load(self.handle, ct.byref(params.c()), ptr, is_dev, D1, n,
+                                 _stream(stream), ct.byref(h)), self.handle)
+        H = Database(self, h, params, n, -(-D1 // params.N))
+        H.D1 = D1
+        self._dbs.add(H)
+        return H
+
+    def pack(self, H: Database, B: int, special_coeff, lwe_b, out, switch_bits: int = 0,
+             stream=None) -> None:
+        """Ring packing: special_coeff [B][n][2][K][N], lwe_b [B][D1] -> out
+        [B][C'][2][K][N] (or [B][C'][2][N] mod 2^switch_bits); device tensors."""
+        _check(lib.pir_pack(self.handle, H.handle, B, _ptr(special_coeff), _ptr(lwe_b), _ptr(out),
+                            switch_bits, _stream(stream)), self.handle)
 
     def load_sdb(self, db, D1: int, D0: int, stream=None) -> ScalarDatabase:
         """Tile an int8 [D1][D0] database (numpy array or torch tensor) for pir_sdb_mul."""

@@ -65,7 +65,8 @@ def test_params_validation_codes():
     assert _status(pir.Params(11, [q[0] + 4096])) == 2                   # not prime
     assert _status(pir.Params(11, [(1 << 28) + 1])) == 2                 # too big
     assert _status(pir.Params(11, [q[0], q[0]])) == 1                    # repeated
-    assert _status(pir.Params(11, q, plain_log2=9)) == 2
+    assert _status(pir.Params(11, q, plain_log2=32)) == 0
+    assert _status(pir.Params(11, q, plain_log2=33)) == 2
     assert _status(pir.Params(11, q, plain_log2=0)) == 2
     assert pir.lib.pir_params_check(None, None) == 1
     assert pir.lib.pir_find_primes(11, 0, 28, None) == 1
