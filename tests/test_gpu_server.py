@@ -134,9 +134,10 @@ def test_budget_limits_admission(env):
 
 def test_ragged_range_count(env):
     # 700 ranges over K N = 2048 slots (2 or 3 slots each; more ranges than
-    # sqrt(K N)): every query still meets every slot once
+    # sqrt(K N)): every query still meets every slot once, also query 4, which
+    # joins mid-lap at step 350 and finishes at step 1049
     pir, ctx, db, rg, raw, queries, expect, sec = env
-    srv = pir.Server(ctx, db, max_batch=2, n_chunks=700)
+    srv = pir.Server(ctx, db, max_batch=3, n_chunks=700)
     got = run(pir, srv, {0: 0, 3: 0, 4: 350}, queries, rg, max_steps=1200)
     for q, a in got.items():
         assert np.array_equal(a, expect[q]), f"query {q}"
