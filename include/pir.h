@@ -227,6 +227,25 @@ typedef struct {
 pir_status pir_answer_batch(pir_ctx *ctx, const pir_job *jobs, size_t n_jobs,
                             pir_stream stream);
 
+/* ---- pir_answer_batch without any device allocation.  For callers that
+ * cannot allocate device memory: code under HIP graph capture, serving loops
+ * and harnesses that forbid hipMalloc.  Same jobs, layouts, results and
+ * errors as pir_answer_batch, but its workspace (the NTT-form queries, the
+ * query tiles, the scan-order answers and the unswitched answers) lives in a
+ * fixed device array of PIR_STATIC_SCRATCH_BYTES that the library holds on
+ * every GPU it runs on until the process ends, instead of the context's
+ * growable workspace.  Calls no allocating routine.  A job list whose
+ * workspace exceeds that size (for instance B*R*2*K*N*4 > 64 MiB for one
+ * batch-1 job) returns PIR_ERR_BUDGET before anything is enqueued.  Every
+ * call on one GPU shares that GPU's array, from any context: calls that
+ * overlap on one GPU (different streams, host threads or contexts) race and
+ * must be ordered by the caller.  Stage profiling (pir_profile_*) does not
+ * time these calls.  PIR_ERR_DEVICE if the array's address could not be
+ * taken when the context was created. */
+#define PIR_STATIC_SCRATCH_BYTES (64u << 20)
+pir_status pir_answer_batch_static(pir_ctx *ctx, const pir_job *jobs, size_t n_jobs,
+                                   pir_stream stream);
+
 /* ---- ring packing of LWE ciphertexts into RLWE ciphertexts (App. C.1,
  * Eq. tiptoe-rp; Sec. 3.5 "Massive parallelism": H C + (0 | G) as
  * (#RNS N)-parallel ceil(D1/N) x 2B x n modular GEMMs over NTT-form

@@ -241,9 +241,9 @@ struct StageTimer {
   hipStream_t s;
   pir_ctx::Rec rec{};
   bool on = false, attached = false;
-  StageTimer(pir_ctx *c, hipStream_t st, uint32_t stage, bool attach = false)
+  StageTimer(pir_ctx *c, hipStream_t st, uint32_t stage, bool attach = false, bool enabled = true)
       : ctx(c), s(st), attached(attach) {
-    if (!(ctx->prof >> stage & 1u)) return;
+    if (!enabled || !(ctx->prof >> stage & 1u)) return;
     rec.stage = stage;
     if (hipEventCreate(&rec.a) != hipSuccess) return;
     if (hipEventCreate(&rec.b) != hipSuccess) {
@@ -487,6 +487,17 @@ pir_status pir_ctx_create(int device, size_t hbm_budget_bytes, pir_ctx **out) {
   ctx->device = device;
   ctx->budget = hbm_budget_bytes;
   ctx->num_cus = cus;
+  {
+    // the device address of the fixed scratch array (pir_answer_batch_static),
+    // taken once per device with that device current
+    DeviceGuard g(device);
+    e = static_scratch_init(device, &ctx->scratch);
+    if (e != hipSuccess) {
+      (void)hipGetLastError();
+      ctx->scratch = nullptr;
+      ctx->scratch_err = hipGetErrorString(e);
+    }
+  }
   *out = ctx;
   return PIR_OK;
 }
@@ -879,37 +890,39 @@ namespace {
 // workspace at `ws` (at least p.bytes()).
 // add (may be null): per job, an addend for the component-1 answer
 // polynomials ([B][C][K][N], NTT form) taken in by the drain (ring packing).
+// timed = false: no stage timers (they create events), for the no-allocation entry.
 pir_status enqueue_batch(pir_ctx *ctx, const pir_job *jobs, size_t n_jobs, uint8_t *ws,
-                         BatchPlan &p, hipStream_t s, const uint32_t *const *add = nullptr) {
+                         BatchPlan &p, hipStream_t s, const uint32_t *const *add = nullptr,
+                         bool timed = true) {
   place_batch(jobs, n_jobs, ws, p);
   for (size_t n = 0; n < n_jobs; ++n) {
     const pir_job &j = jobs[n];
     const DbDesc &d = j.db->desc;
     {
-      StageTimer tm(ctx, s, PIR_STAGE_NTT);
+      StageTimer tm(ctx, s, PIR_STAGE_NTT, false, timed);
       HIP_OR_FAIL(ctx, launch_ntt_copy(j.query_coeff, p.qntt[n], (size_t)j.B * d.R * 2 * d.K, d.K,
                                        d.log2n, d.primes, s));
     }
     if (j.B > 1) {
-      StageTimer tm(ctx, s, PIR_STAGE_PACK);
+      StageTimer tm(ctx, s, PIR_STAGE_PACK, false, timed);
       HIP_OR_FAIL(ctx, launch_pack_query(p.qntt[n], p.qatoms[n], j.B, d.R, d.N, d.K, s));
     }
   }
   // the scans of all jobs: one fused launch per kernel kind
   for (const std::vector<ScanJob> *grp : {&p.b1, &p.mf}) {
     if (grp->empty()) continue;
-    StageTimer tm(ctx, s, PIR_STAGE_SCAN, true);
+    StageTimer tm(ctx, s, PIR_STAGE_SCAN, true, timed);
     HIP_OR_FAIL(ctx, launch_scan(grp->data(), grp->size(), group_cfg(ctx, *grp), s, tm.start(),
                                  tm.stop()));
   }
   for (size_t n = 0; n < n_jobs; ++n) {
     const DbDesc &d = jobs[n].db->desc;
     if (p.sm[n]) {
-      StageTimer tm(ctx, s, PIR_STAGE_UNPACK);
+      StageTimer tm(ctx, s, PIR_STAGE_UNPACK, false, timed);
       const uint32_t P = 2 * jobs[n].B * d.C;
       HIP_OR_FAIL(ctx, launch_unpack_answers(p.sm[n], P, 0, P, d.K * d.N, p.ans[n], s));
     }
-    StageTimer tm(ctx, s, PIR_STAGE_INTT);
+    StageTimer tm(ctx, s, PIR_STAGE_INTT, false, timed);
     const uint32_t *a = add ? add[n] : nullptr;
     if (jobs[n].switch_bits) {
       HIP_OR_FAIL(ctx, launch_intt_switch(p.ans[n], jobs[n].answer_coeff,
@@ -948,6 +961,26 @@ pir_status pir_answer_batch(pir_ctx *ctx, const pir_job *jobs, size_t n_jobs, pi
   DeviceGuard g(ctx->device);
   if ((st = ensure_ws(ctx, p.bytes())) != PIR_OK) return st;
   return enqueue_batch(ctx, jobs, n_jobs, (uint8_t *)ctx->ws, p, (hipStream_t)stream);
+}
+
+pir_status pir_answer_batch_static(pir_ctx *ctx, const pir_job *jobs, size_t n_jobs,
+                                   pir_stream stream) {
+  if (!ctx) return PIR_ERR_INVALID_ARG;
+  if (!jobs && n_jobs) return fail(ctx, PIR_ERR_INVALID_ARG, "jobs is NULL");
+  // the same workspace layout as pir_answer_batch, placed in the fixed array
+  BatchPlan p;
+  pir_status st = plan_batch(ctx, jobs, n_jobs, p);
+  if (st != PIR_OK || n_jobs == 0) return st;
+  if (!ctx->scratch)
+    return fail(ctx, PIR_ERR_DEVICE, "the static scratch array has no device address: %s",
+                ctx->scratch_err.c_str());
+  if (p.bytes() > kStaticScratchBytes)
+    return fail(ctx, PIR_ERR_BUDGET,
+                "the job list needs %zu bytes of workspace; the static scratch array holds %zu",
+                p.bytes(), kStaticScratchBytes);
+  DeviceGuard g(ctx->device);
+  return enqueue_batch(ctx, jobs, n_jobs, (uint8_t *)ctx->scratch, p, (hipStream_t)stream,
+                       nullptr, false);
 }
 
 pir_status pir_pack(pir_ctx *ctx, const pir_db *H, uint32_t B, const uint32_t *special_coeff,

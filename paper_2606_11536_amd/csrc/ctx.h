@@ -20,6 +20,10 @@ struct pir_ctx {
   std::string err;
   void *ws = nullptr;
   size_t ws_bytes = 0;
+  // device address of the library's fixed scratch array on this device
+  // (pir_answer_batch_static), or null with the reason
+  void *scratch = nullptr;
+  std::string scratch_err;
   std::map<std::pair<uint32_t, uint32_t>, uint32_t *> tw_tables;  // (log2n, q) -> [4][N]
   std::map<std::vector<uint32_t>, pir::DevPrime *> prime_sets;       // (log2n, q...) -> [K]
   // stage profiling

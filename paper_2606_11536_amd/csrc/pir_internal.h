@@ -177,4 +177,10 @@ hipError_t launch_fill_tuning(uint32_t *p, size_t n_words, hipStream_t s);
 hipError_t launch_unpack_answers(const uint32_t *sm, uint32_t p_stride, uint32_t p0, uint32_t P,
                                  uint32_t KN, uint32_t *out, hipStream_t s);
 
+// The library's fixed device scratch array (pir_answer_batch_static): its
+// size, and its address on `device`, which must be the current device.  The
+// address is looked up once per device and kept.
+constexpr size_t kStaticScratchBytes = PIR_STATIC_SCRATCH_BYTES;
+hipError_t static_scratch_init(int device, void **ptr);
+
 }  // namespace pir

@@ -65,6 +65,7 @@ SIGNATURES = {
     "pir_sdb_free": (None, [_P]),
     "pir_db_mul": (ct.c_int, [_P, _P, _P, _U32, _P, _P]),
     "pir_answer_batch": (ct.c_int, [_P, ct.POINTER(CJob), ct.c_size_t, _P]),
+    "pir_answer_batch_static": (ct.c_int, [_P, ct.POINTER(CJob), ct.c_size_t, _P]),
     "pir_pack_load": (ct.c_int, [_P, ct.POINTER(CParams), _P, ct.c_int, _U32, _U32, _P,
                                  ct.POINTER(ct.c_void_p)]),
     "pir_pack": (ct.c_int, [_P, _P, _U32, _P, _P, _P, _U32, _P]),
@@ -367,6 +368,12 @@ class Context:
         (coefficient form; with switch_bits the answers are [B][C][2][N] mod 2^bits)."""
         _check(lib.pir_answer_batch(self.handle, self._jobs(jobs), len(jobs), _stream(stream)),
                self.handle)
+
+    def answer_batch_static(self, jobs, stream=None) -> None:
+        """answer_batch with its workspace in the library's fixed device scratch
+        array: allocates nothing (see pir_answer_batch_static)."""
+        _check(lib.pir_answer_batch_static(self.handle, self._jobs(jobs), len(jobs),
+                                           _stream(stream)), self.handle)
 
     def plan(self, jobs, stream=None) -> "Plan":
         """Capture answer_batch(jobs) into a HIP graph (see pir_plan_create)."""
