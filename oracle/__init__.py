@@ -23,6 +23,9 @@ Modules
             SimplePIR round trip (Sec. 2).
 ``pack``    Tiptoe-style ring packing of LWE ciphertexts into RLWE ones,
             H C + (0|G) (App. C.1, Eq. tiptoe-rp; Sec. 3.5).
+``expand``  automorphisms, gadget digits and key switching; the recursive
+            query expansion of ExpPack (Sec. 3.5, App. C.2); RGSW external
+            products, CMux and folding (Sec. 3.2 step 7, Sec. 3.6).
 
 All arithmetic is on exact integers (Python ints, or numpy uint64/int64 with
 every intermediate bounded below 2**63); nothing is approximated.

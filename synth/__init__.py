@@ -24,7 +24,11 @@ drawing the others:
   indistinguishable from uniform, so the scan sees the same distribution);
 * LWE operands of ring packing: the ``a``-part matrix in blocks of 1024 rows
   ``[seed, TAG_LWE_A, block]``, client ``beta``'s ``b``-parts
-  ``[seed, TAG_LWE_B, beta]`` and LWE secret ``[seed, TAG_LWE_SECRET, beta]``.
+  ``[seed, TAG_LWE_B, beta]`` and LWE secret ``[seed, TAG_LWE_SECRET, beta]``;
+* key material of client ``beta`` for expansion and folding: the masks and
+  errors of key-switching key ``level`` ``[seed, TAG_KSK_MASK|TAG_KSK_ERROR,
+  beta, level, row]`` and of RGSW ciphertext ``level`` ``[seed,
+  TAG_RGSW_MASK|TAG_RGSW_ERROR, beta, level, row]``, drawn like the query's.
 
 The error clip ``|e| <= 19`` is the fresh-noise bound ``|e| < 6*sigma`` with
 ``sigma = 3.2`` (cryptographic background, LWE paragraph), applied to RLWE too.
@@ -46,6 +50,11 @@ TAG_ARRIVALS = 0xA7
 TAG_LWE_A = 0x1A
 TAG_LWE_B = 0x1B
 TAG_LWE_SECRET = 0x15
+
+TAG_KSK_MASK = 0x4A
+TAG_KSK_ERROR = 0x4E
+TAG_RGSW_MASK = 0x6A
+TAG_RGSW_ERROR = 0x6E
 
 SIGMA = 3.2
 ERROR_CLIP = 19
@@ -120,22 +129,44 @@ def secret(seed: int, b: int, N: int) -> np.ndarray:
     return _rng(seed, TAG_SECRET, b).integers(-1, 2, size=N, dtype=np.int64)
 
 
-def mask_row(seed: int, b: int, i: int, primes: list[int], N: int) -> np.ndarray:
-    """Uniform mask ``a`` of ciphertext ``i`` of query ``b``: ``[K][N]`` uint64 in ``[0, q_k)``."""
-    g = _rng(seed, TAG_MASK, b, i)
+def _uniform(g: np.random.Generator, primes: list[int], N: int) -> np.ndarray:
     return np.stack([g.integers(0, q, size=N, dtype=np.uint64) for q in primes])
 
 
-def error_row(seed: int, b: int, i: int, N: int, sigma: float = SIGMA,
-              clip: int = ERROR_CLIP) -> np.ndarray:
-    """Rounded-Gaussian error of ciphertext ``i`` of query ``b``: ``N`` int64, ``|e| <= clip``."""
-    g = _rng(seed, TAG_ERROR, b, i)
+def _gaussian(g: np.random.Generator, N: int, sigma: float, clip: int) -> np.ndarray:
     e = np.rint(g.normal(0.0, sigma, size=N)).astype(np.int64)
     bad = np.abs(e) > clip
     while bad.any():
         e[bad] = np.rint(g.normal(0.0, sigma, size=int(bad.sum()))).astype(np.int64)
         bad = np.abs(e) > clip
     return e
+
+
+def mask_row(seed: int, b: int, i: int, primes: list[int], N: int) -> np.ndarray:
+    """Uniform mask ``a`` of ciphertext ``i`` of query ``b``: ``[K][N]`` uint64 in ``[0, q_k)``."""
+    return _uniform(_rng(seed, TAG_MASK, b, i), primes, N)
+
+
+def error_row(seed: int, b: int, i: int, N: int, sigma: float = SIGMA,
+              clip: int = ERROR_CLIP) -> np.ndarray:
+    """Rounded-Gaussian error of ciphertext ``i`` of query ``b``: ``N`` int64, ``|e| <= clip``."""
+    return _gaussian(_rng(seed, TAG_ERROR, b, i), N, sigma, clip)
+
+
+def key_masks(seed: int, kind: str, beta: int, level: int, rows: int, primes: list[int],
+              N: int) -> np.ndarray:
+    """Masks of client ``beta``'s key-switching key (``kind = "ksk"``) or RGSW ciphertext
+    (``"rgsw"``) number ``level``: ``[rows][K][N]`` uint64 uniform in ``[0, q_k)``."""
+    tag = {"ksk": TAG_KSK_MASK, "rgsw": TAG_RGSW_MASK}[kind]
+    return np.stack([_uniform(_rng(seed, tag, beta, level, r), primes, N) for r in range(rows)])
+
+
+def key_errors(seed: int, kind: str, beta: int, level: int, rows: int, N: int,
+               sigma: float = SIGMA, clip: int = ERROR_CLIP) -> np.ndarray:
+    """Errors of the same rows: ``[rows][N]`` int64 rounded Gaussians, ``|e| <= clip``."""
+    tag = {"ksk": TAG_KSK_ERROR, "rgsw": TAG_RGSW_ERROR}[kind]
+    return np.stack([_gaussian(_rng(seed, tag, beta, level, r), N, sigma, clip)
+                     for r in range(rows)])
 
 
 def indices(seed: int, B: int, R: int) -> np.ndarray:
