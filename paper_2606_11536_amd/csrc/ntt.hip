@@ -93,7 +93,9 @@ __device__ __forceinline__ void round_compute(double (&x)[Geo<LOGN>::E], uint32_
       const int f = e + (1 << u);
       const uint32_t idx = ridx<LOGN, INV, R>(tid, e);
       const uint32_t ti = (uint32_t)(G::N + idx) >> (logh + 1);
-      const double w = (double)tw[ti];
+      // a global (not flat) load: the table pointer comes from the prime
+      // record, so the compiler cannot tell its address space by itself
+      const double w = (double)((const __attribute__((address_space(1))) uint32_t *)tw)[ti];
       const double X = x[e], Y = x[f];
       if (!INV) {
         const double T = mulmod_f64(Y, w, q, inv_q);
