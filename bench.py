@@ -65,6 +65,10 @@ SCALAR = dict(D1=1 << 18, D0=1 << 16, batches=[1, 16, 32])
 # (the 2^18 rows of the 16 GiB scalar database), LWE dimension n = 1280,
 # packed into RLWE ciphertexts of N = 4096 under two primes, p = 2^18
 PACK = dict(log2n=12, K=2, D1=1 << 18, n=1280, p_log2=18, B=32)
+# query expansion of ExpPack (one ciphertext per client expanded into the n = 1280
+# special ciphertexts of ring packing, N = 4096, two primes, gadget 2^14 x 4 digits)
+# and RGSW folding of D = 2^8 ciphertexts per client (the paper's log2 D_r = 8 rounds)
+EXPAND = dict(log2n=12, K=2, n=1280, B=32, base_log=14, n_digits=4, fold_L=8)
 # three databases of uneven shape in one batch: (log2n, K, R, C)
 MULTIDB = [(12, 2, 1024, 512), (11, 2, 3000, 700), (11, 2, 256, 4096)]
 
@@ -755,6 +759,103 @@ def pack(args) -> dict:
     return res
 
 
+def expand(args) -> dict:
+    """Query expansion (pir_expand) and RGSW folding (pir_fold) of a batch of clients."""
+    import torch
+
+    from paper_2606_11536_amd import pir
+    cfg = EXPAND
+    log2n, K, n, B, bl, nd, L = (cfg[k] for k in ("log2n", "K", "n", "B", "base_log",
+                                                   "n_digits", "fold_L"))
+    N = 1 << log2n
+    levels = max(1, (n - 1).bit_length())
+    # key switches per client: every output of every level below n
+    n_ks = sum(min(2 << j, n) for j in range(levels))
+    cpu = None
+    if not args.no_cpu_baseline:
+        from oracle import expand as ex
+        from oracle import params as op
+        qs = op.ntt_primes(N, K)
+        psis = [op.psi_min(N, q) for q in qs]
+        rng = np.random.default_rng(args.seed)
+        ct = np.stack([np.stack([rng.integers(0, q, N, dtype=np.uint64) for q in qs])
+                       for _ in range(2)])
+        key = np.stack([np.stack([np.stack([rng.integers(0, q, N, dtype=np.uint64) for q in qs])
+                                  for _ in range(2)]) for _ in range(nd)])
+        reps, t = 0, time.perf_counter()
+        while time.perf_counter() - t < 10.0:
+            ex.subs(ct, ex.expansion_exponent(N, 0), key, qs, psis, bl)
+            reps += 1
+        sec = (time.perf_counter() - t) / reps
+        cpu = {"value": round(1.0 / (sec * n_ks), 6), "unit": "clients/s", "cores": 1,
+               "kind": "oracle",
+               "sample": f"oracle key switch (automorphism, {nd} gadget digits, N={N}, {K} "
+                         f"primes) x{reps} in {sec * reps:.1f} s on one core, scaled by the "
+                         f"{n_ks} key switches of one client's expansion"}
+    ctx = pir.Context(0)
+    primes = pir.find_primes(log2n, K, 28)
+    params = pir.Params(log2n, primes, 8)
+    dev = torch.device("cuda:0")
+    gen = torch.Generator(device="cuda").manual_seed(args.seed)
+
+    def uniform(shape):
+        t = torch.empty(shape + (K, N), dtype=torch.int32, device=dev)
+        for k, q in enumerate(primes):
+            t[..., k, :].copy_(torch.randint(0, q, shape + (N,), generator=gen, device=dev,
+                                             dtype=torch.int64).to(torch.int32))
+        return t
+
+    keys = ctx.load_expand_keys(params, uniform((B, levels, nd, 2)), B, levels, bl, nd)
+    ct = uniform((B, 2))
+    out = torch.empty((B, n, 2, K, N), dtype=torch.int32, device=dev)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    for _ in range(args.warmup):
+        ctx.expand(keys, ct, n, out)
+    torch.cuda.synchronize()
+    e0.record()
+    for _ in range(args.steps):
+        ctx.expand(keys, ct, n, out)
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / args.steps
+    keys.free()
+    del out
+    torch.cuda.empty_cache()
+    D = 1 << L
+    cts = uniform((B, D, 2))
+    rg = uniform((B, L, 2 * nd, 2))
+    fo = torch.empty((B, 2, K, N), dtype=torch.int32, device=dev)
+    for _ in range(args.warmup):
+        ctx.fold(params, cts, D, rg, bl, nd, B, fo)
+    torch.cuda.synchronize()
+    e0.record()
+    for _ in range(args.steps):
+        ctx.fold(params, cts, D, rg, bl, nd, B, fo)
+    e1.record()
+    torch.cuda.synchronize()
+    fold_ms = e0.elapsed_time(e1) / args.steps
+    ctx.close()
+    res = {
+        "metric": "query expansion: clients expanded per second (n special ciphertexts each)",
+        "value": round(B * 1e3 / ms, 2), "unit": "clients/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(ms, 4),
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "u32",
+        "data": "synthetic",
+        "config": {"workload": (f"ExpPack expansion: one RLWE ciphertext per client into n={n} "
+                                f"ciphertexts ({levels} levels, {n_ks} key switches per client), "
+                                f"N={N}, {K} primes < 2^28, gadget 2^{bl} x {nd} digits, B={B} "
+                                f"clients (keys and ciphertexts uniform)"),
+                   "N": N, "primes": primes, "n": n, "B": B, "base_log": bl, "n_digits": nd},
+        "key_switches_per_s": round(B * n_ks * 1e3 / ms, 1),
+        "fold": {"D": D, "rounds": L, "B": B, "ms": round(fold_ms, 4),
+                 "clients_per_s": round(B * 1e3 / fold_ms, 2),
+                 "external_products_per_s": round(B * (D - 1) * 1e3 / fold_ms, 1)},
+    }
+    if cpu is not None:
+        res["cpu_baseline"] = cpu
+    return res
+
+
 def multidb(args) -> dict:
     """Three uneven databases, 1..64 queries each, one fused batch, HIP-graph replays."""
     import torch
@@ -891,7 +992,7 @@ def main() -> int:
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--workload", default="headline",
                     choices=["headline"] + sorted(WORKLOADS) + ["serving", "multidb", "drain",
-                                                                "scalar", "pack"])
+                                                                "scalar", "pack", "expand"])
     ap.add_argument("--serve-seconds", type=float, default=3.0)
     ap.add_argument("--serve-max-requests", type=int, default=1500)
     ap.add_argument("--seed", type=int, default=0)
@@ -911,9 +1012,9 @@ def main() -> int:
     if args.calibrate_copy:
         calibrate_copy()
         return 0
-    if args.workload in ("serving", "multidb", "drain", "scalar", "pack"):
+    if args.workload in ("serving", "multidb", "drain", "scalar", "pack", "expand"):
         fn = {"serving": serve, "multidb": multidb, "drain": drain, "scalar": scalar,
-              "pack": pack}[args.workload]
+              "pack": pack, "expand": expand}[args.workload]
         print(json.dumps(fn(args)), flush=True)
         return 0
 

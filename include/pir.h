@@ -278,6 +278,59 @@ pir_status pir_pack_load(pir_ctx *ctx, const pir_params *params, const uint32_t 
 pir_status pir_pack(pir_ctx *ctx, const pir_db *H, uint32_t B, const uint32_t *special_coeff,
                     const uint32_t *lwe_b, uint32_t *out, uint32_t switch_bits, pir_stream stream);
 
+/* ---- query expansion (ExpPack: Sec. 3.5 "Expansion-based ring packing",
+ * App. C.2) and RGSW folding (Sec. 3.2 step 7; Sec. 3.6 step 7).
+ *
+ * Gadget (both calls): a coefficient of Z_Q, Q = q0 q1 (one or two primes), is
+ * recombined by CRT, centred to (-Q/2, Q/2] and written in n_digits balanced
+ * digits of base 2^base_log (the low ones in [-2^(base_log-1),
+ * 2^(base_log-1)), the top one taking the rest); g_d = 2^(base_log d).
+ * Requires 2^(base_log n_digits) >= Q, 1 <= base_log <= 30,
+ * 1 <= n_digits <= PIR_MAX_DIGITS, and one or two primes (else UNSUPPORTED).
+ * Ciphertexts are (a, b) with phase a s + b, layout [2][K][N] coefficient form,
+ * residues < q_k.
+ *
+ * pir_expand_keys_load: the key-switching keys of B clients, keys
+ * [B][levels][n_digits][2][K][N] coefficient form (host or device per
+ * keys_is_device): key j of a client switches from s(X^(N/2^j + 1)) to s, row
+ * d = (a_d, -a_d s + e_d + g_d s(X^(N/2^j + 1))).  They are copied and held in
+ * NTT form (B levels n_digits 2 K N 4 bytes) until pir_expand_keys_free.
+ * 1 <= levels <= log2 N.  A host copy is complete on return; a device source
+ * must stay valid until `stream` passes the load.
+ *
+ * pir_expand: every client's ciphertext ct_coeff [B][2][K][N] of
+ * sum_i m_i X^i becomes out [B][n][2][K][N], output i encrypting the constant
+ * m_i (1 <= n <= N): the input is multiplied by 2^-l mod q_k (l =
+ * ceil(log2 n), at least 1, at most the keys' levels) and taken through l
+ * levels of the recursive expansion; at level j each ciphertext c becomes
+ * c + Subs(c, N/2^j + 1) at its own index k and c' + Subs(c', N/2^j + 1),
+ * c' = c X^(-2^j), at index k + 2^j, Subs = automorphism X -> X^g then key
+ * switch.  out feeds pir_pack's special ciphertexts directly.  Asynchronous on
+ * `stream`; uses context workspace of about
+ * B (2 min(2^(l-1), n) 2 + n (n_digits + 2)) K N 4 bytes.
+ *
+ * pir_fold: for each of B clients, selects one of D = 2^L ciphertexts
+ * cts_coeff [B][D][2][K][N] with L RGSW ciphertexts rgsw_coeff
+ * [B][L][2 n_digits][2][K][N] (coefficient form; row d = (a_d + m g_d, -a_d s +
+ * e_d), row n_digits + d = (a_d', -a_d' s + e_d' + m g_d), m the index bit):
+ * round j replaces entries (2i, 2i + 1) by ct_2i + RGSW_j [x] (ct_2i+1 - ct_2i),
+ * the external product being sum_d D_d(a) row_d + D_d(b) row_{n_digits + d}.
+ * out [B][2][K][N].  D = 1 copies.  Asynchronous on `stream`; context
+ * workspace about B (L 2 n_digits 2 + D/2 (6 + 2 n_digits)) K N 4 bytes.
+ * Errors: INVALID_ARG, UNSUPPORTED, BUDGET, OUT_OF_MEMORY, DEVICE. */
+#define PIR_MAX_DIGITS 16u
+typedef struct pir_keys pir_keys;
+pir_status pir_expand_keys_load(pir_ctx *ctx, const pir_params *params, const uint32_t *keys,
+                                int keys_is_device, uint32_t B, uint32_t levels,
+                                uint32_t base_log, uint32_t n_digits, pir_stream stream,
+                                pir_keys **out);
+void pir_expand_keys_free(pir_keys *keys);
+pir_status pir_expand(pir_ctx *ctx, const pir_keys *keys, const uint32_t *ct_coeff, uint32_t n,
+                      uint32_t *out, pir_stream stream);
+pir_status pir_fold(pir_ctx *ctx, const pir_params *params, const uint32_t *cts_coeff, uint32_t D,
+                    const uint32_t *rgsw_coeff, uint32_t base_log, uint32_t n_digits, uint32_t B,
+                    uint32_t *out, pir_stream stream);
+
 /* ---- batch steady state: a job list captured once into a HIP graph.
  * pir_plan_create records what pir_answer_batch(jobs) enqueues (all kernel
  * launches, with the scan variants chosen at that moment) into a graph with

@@ -32,7 +32,8 @@ FLAGS = [
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
     "-Wall", "-Wno-unused-function",
 ]
-SOURCES = ["ntt.hip", "layout.hip", "scan.hip", "sgemm.hip", "scratch.hip", "api.cpp", "server.cpp"]
+SOURCES = ["ntt.hip", "layout.hip", "scan.hip", "sgemm.hip", "scratch.hip", "expand.hip", "api.cpp",
+           "server.cpp", "expand_api.cpp"]
 
 
 def _compile(src: str) -> str:

@@ -107,6 +107,10 @@ uint32_t shoup(uint32_t w, uint32_t q) { return (uint32_t)(((uint64_t)w << 32) /
 
 bool log2n_ok(uint32_t l) { return l >= PIR_MIN_LOG2_N && l <= PIR_MAX_LOG2_N; }
 
+}  // namespace
+
+namespace pir {
+
 pir_status check_params(pir_ctx *ctx, const pir_params *p) {
   if (!p) return fail(ctx, PIR_ERR_INVALID_ARG, "params is NULL");
   if (!log2n_ok(p->log2_n))
@@ -129,9 +133,6 @@ pir_status check_params(pir_ctx *ctx, const pir_params *p) {
   return PIR_OK;
 }
 
-}  // namespace
-
-namespace pir {
 // ------------------------------------------------------- device memory ----
 pir_status dev_alloc(pir_ctx *ctx, void **p, size_t bytes, const char *what) {
   if (ctx->budget && ctx->held + bytes > ctx->budget)
@@ -151,10 +152,6 @@ void dev_free(pir_ctx *ctx, void *p, size_t bytes) {
   ctx->held -= bytes;
 }
 
-}  // namespace pir
-
-namespace {
-
 pir_status ensure_ws(pir_ctx *ctx, size_t bytes) {
   if (ctx->ws_bytes >= bytes) return PIR_OK;
   HIP_OR_FAIL(ctx, hipDeviceSynchronize());
@@ -168,7 +165,7 @@ pir_status ensure_ws(pir_ctx *ctx, size_t bytes) {
   return PIR_OK;
 }
 
-}  // namespace
+}  // namespace pir
 
 namespace pir {
 // Device table of per-prime constants for (log2n, primes).

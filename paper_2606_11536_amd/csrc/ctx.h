@@ -65,6 +65,11 @@ namespace pir {
 pir_status fail(pir_ctx *ctx, pir_status s, const char *fmt, ...);
 pir_status dev_alloc(pir_ctx *ctx, void **p, size_t bytes, const char *what);
 void dev_free(pir_ctx *ctx, void *p, size_t bytes);
+// The context workspace grown to at least `bytes` (synchronizes the device
+// when it grows).
+pir_status ensure_ws(pir_ctx *ctx, size_t bytes);
+// Validation of ring parameters (UNSUPPORTED / INVALID_ARG with a message).
+pir_status check_params(pir_ctx *ctx, const pir_params *p);
 // Device constants for (log2n, primes), cached on the context.
 pir_status prime_set(pir_ctx *ctx, const pir_params *p, const DevPrime **out);
 // The chosen scan variant for (db shape, B).

@@ -69,6 +69,11 @@ SIGNATURES = {
     "pir_pack_load": (ct.c_int, [_P, ct.POINTER(CParams), _P, ct.c_int, _U32, _U32, _P,
                                  ct.POINTER(ct.c_void_p)]),
     "pir_pack": (ct.c_int, [_P, _P, _U32, _P, _P, _P, _U32, _P]),
+    "pir_expand_keys_load": (ct.c_int, [_P, ct.POINTER(CParams), _P, ct.c_int, _U32, _U32, _U32,
+                                        _U32, _P, ct.POINTER(ct.c_void_p)]),
+    "pir_expand_keys_free": (None, [_P]),
+    "pir_expand": (ct.c_int, [_P, _P, _P, _U32, _P, _P]),
+    "pir_fold": (ct.c_int, [_P, ct.POINTER(CParams), _P, _U32, _P, _U32, _U32, _U32, _P, _P]),
     "pir_scan_variants": (ct.c_uint32, [_U32]),
     "pir_scan_select": (ct.c_int, [_P, _P, _U32, _U32]),
     "pir_scan_kernel": (ct.c_char_p, [_P, _P, _U32]),
@@ -189,6 +194,20 @@ class ScalarDatabase:
         self.handle = None
 
 
+class ExpandKeys:
+    """Key-switching keys of B clients for pir_expand, held in NTT form by libpir."""
+
+    def __init__(self, ctx: "Context", handle: ct.c_void_p, params: Params, B: int, levels: int,
+                 base_log: int, n_digits: int):
+        self.ctx, self.handle, self.params = ctx, handle, params
+        self.B, self.levels, self.base_log, self.n_digits = B, levels, base_log, n_digits
+
+    def free(self) -> None:
+        if self.handle and self.ctx.handle:
+            lib.pir_expand_keys_free(self.handle)
+        self.handle = None
+
+
 class Database:
     """A device-resident NTT-form database owned by libpir."""
 
@@ -306,6 +325,38 @@ class Context:
         [B][C'][2][K][N] (or [B][C'][2][N] mod 2^switch_bits); device tensors."""
         _check(lib.pir_pack(self.handle, H.handle, B, _ptr(special_coeff), _ptr(lwe_b), _ptr(out),
                             switch_bits, _stream(stream)), self.handle)
+
+    def load_expand_keys(self, params: Params, keys, B: int, levels: int, base_log: int,
+                         n_digits: int, stream=None) -> ExpandKeys:
+        """Key-switching keys [B][levels][n_digits][2][K][N] (coefficient form; numpy array
+        or torch tensor) for pir_expand."""
+        h = ct.c_void_p()
+        if hasattr(keys, "data_ptr"):
+            assert keys.is_contiguous() and keys.element_size() == 4
+            is_dev, ptr = int(keys.is_cuda), ct.c_void_p(keys.data_ptr())
+        else:
+            import numpy as np
+            keys = np.ascontiguousarray(keys, dtype=np.uint32)
+            is_dev, ptr = 0, keys.ctypes.data_as(ct.c_void_p)
+        _check(lib.pir_expand_keys_load(self.handle, ct.byref(params.c()), ptr, is_dev, B, levels,
+                                        base_log, n_digits, _stream(stream), ct.byref(h)),
+               self.handle)
+        k = ExpandKeys(self, h, params, B, levels, base_log, n_digits)
+        self._dbs.add(k)
+        return k
+
+    def expand(self, keys: ExpandKeys, ct_coeff, n: int, out, stream=None) -> None:
+        """Expansion: ct_coeff [B][2][K][N] -> out [B][n][2][K][N] (device tensors)."""
+        _check(lib.pir_expand(self.handle, keys.handle, _ptr(ct_coeff), n, _ptr(out),
+                              _stream(stream)), self.handle)
+
+    def fold(self, params: Params, cts, D: int, rgsw, base_log: int, n_digits: int, B: int, out,
+             stream=None) -> None:
+        """RGSW folding: cts [B][D][2][K][N], rgsw [B][log2 D][2 n_digits][2][K][N] -> out
+        [B][2][K][N] (device tensors, coefficient form)."""
+        _check(lib.pir_fold(self.handle, ct.byref(params.c()), _ptr(cts), D,
+                            _ptr(rgsw) if rgsw is not None else None, base_log, n_digits, B,
+                            _ptr(out), _stream(stream)), self.handle)
 
     def load_sdb(self, db, D1: int, D0: int, stream=None) -> ScalarDatabase:
         """Tile an int8 [D1][D0] database (numpy array or torch tensor) for pir_sdb_mul."""
