@@ -88,11 +88,14 @@ __device__ __forceinline__ uint32_t quad_sum_mod(uint32_t s, uint32_t q) {
 }
 
 // x moved from the lane given by the quad permutation CTRL, 64 bits at a time.
+// Every lane's source lies in its own quad, so no lane reads an invalid source
+// and the plain move (no old value to preserve) is exact; it spares the
+// register initialisation an update with an old value costs.
 template <int CTRL>
 __device__ __forceinline__ double quad_perm_f64(double x) {
   const uint64_t u = __builtin_bit_cast(uint64_t, x);
-  const uint32_t lo = (uint32_t)__builtin_amdgcn_update_dpp(0, (int)(uint32_t)u, CTRL, 0xF, 0xF, false);
-  const uint32_t hi = (uint32_t)__builtin_amdgcn_update_dpp(0, (int)(uint32_t)(u >> 32), CTRL, 0xF, 0xF, false);
+  const uint32_t lo = (uint32_t)__builtin_amdgcn_mov_dpp((int)(uint32_t)u, CTRL, 0xF, 0xF, true);
+  const uint32_t hi = (uint32_t)__builtin_amdgcn_mov_dpp((int)(uint32_t)(u >> 32), CTRL, 0xF, 0xF, true);
   return __builtin_bit_cast(double, ((uint64_t)hi << 32) | lo);
 }
 
