@@ -34,6 +34,9 @@
  *    guaranteed in the outputs; pir_last_error(ctx) describes the failure.
  *    No C++ exception crosses this boundary.
  *  - A context is not thread-safe: use one context per host thread.
+ *  - Calls that use the context workspace (documented below) share one
+ *    buffer: work enqueued by such calls on different streams must not run at
+ *    the same time (use one stream, or order the streams with events).
  */
 #ifndef PIR_H_
 #define PIR_H_
