@@ -63,7 +63,10 @@ __device__ __forceinline__ int64_t crt_centred(uint32_t x0, uint32_t x1, const G
 }
 
 // Writes the n_digits digits of x (|x| <= (Q-1)/2) at out[d * stride] as
-// residues mod q_k (K rows of N words apart).
+// residues mod q_k (K rows of N words apart).  A digit can exceed a small
+// prime (lower digits reach 2^(base_log-1), up to 2^29; the top digit takes
+// the rest, below 2^29 because the gadget covers Q < 2^56 with base_log <= 30),
+// so each is reduced exactly: it is an integer below 2^53, exact as a double.
 __device__ __forceinline__ void put_digits(int64_t x, uint32_t *out, size_t dstride,
                                            uint32_t N, const GadgetArgs &g) {
   const int64_t B = (int64_t)1 << g.base_log, half = B >> 1;
@@ -74,8 +77,8 @@ __device__ __forceinline__ void put_digits(int64_t x, uint32_t *out, size_t dstr
       if (r >= half) r -= B;
       x = (x - r) >> g.base_log;
     }
-    out[d * dstride] = (uint32_t)(r < 0 ? r + (int64_t)g.q0 : r);
-    if (g.K == 2) out[d * dstride + N] = (uint32_t)(r < 0 ? r + (int64_t)g.q1 : r);
+    out[d * dstride] = canon_f64((double)r, (double)g.q0, g.inv_q0);
+    if (g.K == 2) out[d * dstride + N] = canon_f64((double)r, (double)g.q1, g.inv_q1);
   }
 }
 

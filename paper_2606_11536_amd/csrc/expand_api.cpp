@@ -63,6 +63,8 @@ pir_status gadget_of(pir_ctx *ctx, const pir_params *p, uint32_t base_log, uint3
   g->q1 = g->K == 2 ? p->primes[1] : 1;
   g->Q = (uint64_t)g->q0 * g->q1;
   g->c = g->K == 2 ? (double)inv_mod(g->q0, g->q1) : 0.0;
+  g->inv_q0 = 1.0 / (double)g->q0;
+  g->inv_q1 = 1.0 / (double)g->q1;
   g->base_log = base_log;
   g->n_digits = n_digits;
   const uint32_t bits = base_log * n_digits;

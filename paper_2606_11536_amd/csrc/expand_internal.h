@@ -15,6 +15,7 @@ struct GadgetArgs {
   uint32_t q0, q1;           // primes (q1 = 1 for K = 1)
   uint64_t Q;                // q0 q1
   double c;                  // q0^-1 mod q1 (K = 2)
+  double inv_q0, inv_q1;     // 1 / q0, 1 / q1 (1 / q1 unused for K = 1)
   uint32_t base_log, n_digits;
 };
 

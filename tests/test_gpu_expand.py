@@ -213,6 +213,43 @@ def test_fold_matches_oracle(ctx, log2n, L, B):
         assert np.array_equal(dec, msgs[b, int(index[b])])
 
 
+def _small_ring(log2n=10):
+    # two small NTT primes (= 1 mod 2N, Q ~ 2^29): gadget digits of 2^16 exceed
+    # both, so the digit residues need a true reduction, not one added q
+    from pirtest import Ring
+    N = 1 << log2n
+    qs = [12289, 40961]
+    assert all(q % (2 * N) == 1 for q in qs)
+    return Ring(log2n, qs, [op.psi_min(N, q) for q in qs], op.scale(qs, 256))
+
+
+def test_expand_small_primes(ctx):
+    rg, n, B, base_log, n_digits = _small_ring(), 12, 2, 16, 2
+    l = ex.levels(n)
+    keys, _ = _keys(91, B, l, rg, base_log, n_digits)
+    ct = _uniform_ct(91, B, rg)
+    K = ctx.load_expand_keys(_params(rg), keys, B, l, base_log, n_digits)
+    out = empty_dev((B, n, 2, rg.K, rg.N))
+    ctx.expand(K, to_dev(ct), n, out)
+    got = to_host(out)
+    for b in range(B):
+        assert np.array_equal(got[b], ex.expand(ct[b], keys[b], n, rg.primes, rg.psis, base_log))
+    K.free()
+
+
+def test_fold_small_primes(ctx):
+    rg, L, B, base_log, n_digits = _small_ring(), 3, 2, 16, 2
+    D = 1 << L
+    index = synth.indices(93, B, D)
+    rg_s, _ = _rgsws(93, B, L, index, rg, base_log, n_digits)
+    cts = np.stack([_uniform_ct(94 + b, D, rg) for b in range(B)])
+    out = empty_dev((B, 2, rg.K, rg.N))
+    ctx.fold(_params(rg), to_dev(cts), D, to_dev(rg_s), base_log, n_digits, B, out)
+    got = to_host(out)
+    for b in range(B):
+        assert np.array_equal(got[b], ex.fold(cts[b], rg_s[b], rg.primes, rg.psis, base_log))
+
+
 def test_arguments(ctx):
     from paper_2606_11536_amd import pir
     rg = ring(10, 2)
