@@ -112,6 +112,34 @@ def test_db_mul_extreme_residues(ctx):
         assert np.array_equal(to_host(out), exp)
 
 
+def test_small_primes(ctx):
+    """Two small primes (12289, 40961: residues of two 7-bit limbs, the upper
+    limb planes all zero) with mostly all-255 bytes and all-(q-1) queries;
+    every batch-1 and batched variant."""
+    from paper_2606_11536_amd import pir
+    from pirtest import Ring
+    from oracle import params as op
+    log2n, R, C = 10, 1000, 10
+    N = 1 << log2n
+    qs = [12289, 40961]
+    rg = Ring(log2n, qs, [op.psi_min(N, q) for q in qs], op.scale(qs, 256))
+    raw = np.full((R, C, N), 255, dtype=np.uint8)
+    raw[:, :, ::7] = synth.db_bytes(41, R, C, N)[:, :, ::7]
+    db = ctx.load_db(rg.pir_params(), raw, R, C)
+    dbn = osc.db_ntt(raw, rg.primes, rg.psis)
+    for B in (1, 3):
+        q_hat = np.stack([np.full((B, R, 2, N), q - 1, dtype=np.uint64) for q in qs], axis=3)
+        q_hat[..., ::5] = residues(np.random.default_rng(B), (B, R, 2), rg)[..., ::5]
+        exp = osc.db_mul(dbn, q_hat, rg.primes)
+        qd = to_dev(q_hat)
+        for v in range(pir.scan_variants(B)):
+            ctx.scan_select(db, B, v)
+            out = empty_dev((B, C, 2, rg.K, N))
+            ctx.db_mul(db, qd, B, out)
+            assert np.array_equal(to_host(out), exp), f"B={B} variant {v}"
+    db.free()
+
+
 @pytest.mark.parametrize("seed", [0, 5, 15])
 def test_tiny_workload_end_to_end(ctx, seed):
     """N=1024, one prime, 16 x 16 DB, one query: GPU answer == oracle; decrypts to row seed % 16."""
