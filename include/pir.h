@@ -405,7 +405,9 @@ pir_status pir_server_submit(pir_server *srv, const uint32_t *query_coeff, uint3
 
 /* One step on `stream`: admit queued queries into free slots, scan the next
  * range for all active queries, finish queries that completed their lap.
- * Asynchronous.  *admitted / *finished (may be NULL) count this step's events. */
+ * Asynchronous.  *admitted / *finished (may be NULL) count this step's events.
+ * Steps of one server share its state (query columns, answers, the admission
+ * scratch): give every step the same stream, or order the streams. */
 pir_status pir_server_step(pir_server *srv, pir_stream stream, uint32_t *admitted,
                            uint32_t *finished);
 
