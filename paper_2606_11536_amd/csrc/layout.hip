@@ -140,41 +140,66 @@ __global__ __launch_bounds__(256) void k_pack_query(const uint32_t *__restrict__
   }
 }
 
-// One query [R][2][K][N] into columns 2*col_slot + comp of the query atoms:
-// thread = (k, t, ib, half, comp, b) writes the 16 bytes of lane
-// 32*half + 4*cc + b, cc = (2*col_slot + comp) % 8, in atom (k, t, ib, cb).
+// One query [R][2][K][N] into its columns 2 col_slot + comp of column-block-
+// major query atoms [K][N][n_cb][n_ib] (the server's layout).  In an atom the
+// query owns lanes 32 half + 4 cc + b for cc = cc0, cc0 + 1 and limbs b < 4:
+// two 128-byte lines, one per half.  Column-block-major order puts a slot's
+// n_ib atoms of one column block next to each other, so the lines a block
+// writes for one slot lie within a few KiB.
+// Block = (32 slots, kPqIB row blocks, prime k): rows i of both components are
+// staged in LDS as 128-byte runs along t, then every line is written by 8
+// lanes, 16 bytes each.
+constexpr uint32_t kPqIB = 4;  // row blocks per workgroup
+
 __global__ __launch_bounds__(256) void k_pack_query_slot(const uint32_t *__restrict__ q,
                                                          uint8_t *__restrict__ qatoms,
                                                          uint32_t col_slot, uint32_t n_cb,
                                                          uint32_t R, uint32_t N, uint32_t K,
                                                          uint32_t n_ib) {
-  const size_t total = (size_t)K * N * n_ib * 16;
-  const size_t idx = blockIdx.x * (size_t)blockDim.x + threadIdx.x;
-  if (idx >= total) return;
-  // t fastest, so consecutive threads read consecutive residues
-  const uint32_t t = idx % N;
-  size_t rest = idx / N;
-  const uint32_t sub = rest % 16;
-  rest /= 16;
-  const uint32_t ib = rest % n_ib;
-  const uint32_t k = rest / n_ib;
-  const uint32_t half = sub >> 3, comp = (sub >> 2) & 1, b = sub & 3;
-  const uint32_t col = 2 * col_slot + comp, cb = col / 8, cc = col % 8;
-  uint32_t word[4];
+  // row r = (ibl 32 + il) 2 + comp, t along the pitch
+  __shared__ uint32_t lds[kPqIB * 32 * 2 * kPad];
+  const uint32_t tid = threadIdx.x;
+  const uint32_t t0 = blockIdx.x * 32, ib0 = blockIdx.y * kPqIB, k = blockIdx.z;
+  const uint32_t tt = tid & 31, p = tid >> 5;
+  uint32_t v[32];
 #pragma unroll
-  for (int q4 = 0; q4 < 4; ++q4) {
-    uint32_t acc = 0;
-#pragma unroll
-    for (int e = 0; e < 4; ++e) {
-      const uint32_t i = ib * 32 + half * 16 + 4 * q4 + e;
-      const uint32_t v = i < R ? q[(((size_t)i * 2 + comp) * K + k) * N + t] : 0u;
-      acc |= ((v >> (7 * b)) & 127u) << (8 * e);
-    }
-    word[q4] = acc;
+  for (uint32_t r = 0; r < 32; ++r) {
+    const uint32_t row = p + 8 * r;
+    const uint32_t comp = row & 1, il = (row >> 1) & 31, ibl = row >> 6;
+    const uint32_t i = (ib0 + ibl) * 32 + il;
+    const bool ok = i < R;
+    const size_t at = (((size_t)i * 2 + comp) * K + k) * N + t0 + tt;
+    v[r] = q[ok ? at : 0] & (ok ? ~0u : 0u);
   }
-  const size_t atom = (((size_t)k * N + t) * n_ib + ib) * n_cb + cb;
-  reinterpret_cast<uint4 *>(qatoms)[atom * 64 + half * 32 + cc * 4 + b] =
-      make_uint4(word[0], word[1], word[2], word[3]);
+#pragma unroll
+  for (uint32_t r = 0; r < 32; ++r) lds[(p + 8 * r) * kPad + tt] = v[r];
+  __syncthreads();
+  const uint32_t cb = (2 * col_slot) / kCB, cc0 = (2 * col_slot) % kCB;
+  uint4 *out = reinterpret_cast<uint4 *>(qatoms);
+  // line = (tl, ibl, half), half fastest: a wave's 8 lines are one slot's
+  // 4 consecutive atoms, both halves
+#pragma unroll
+  for (uint32_t rr = 0; rr < 8; ++rr) {
+    const uint32_t w = tid + 256 * rr;
+    const uint32_t part = w & 7, line = w >> 3;
+    const uint32_t half = line & 1, ibl = (line >> 1) & (kPqIB - 1), tl = line >> 3;
+    const uint32_t comp = part >> 2, b = part & 3;
+    uint32_t word[4];
+#pragma unroll
+    for (int q4 = 0; q4 < 4; ++q4) {
+      uint32_t acc = 0;
+#pragma unroll
+      for (int e = 0; e < 4; ++e) {
+        const uint32_t row = (ibl * 32 + half * 16 + 4 * q4 + e) * 2 + comp;
+        acc |= ((lds[row * kPad + tl] >> (7 * b)) & 127u) << (8 * e);
+      }
+      word[q4] = acc;
+    }
+    if (ib0 + ibl < n_ib) {
+      const size_t atom = (((size_t)k * N + t0 + tl) * n_cb + cb) * n_ib + ib0 + ibl;
+      out[atom * 64 + half * 32 + cc0 * 4 + part] = make_uint4(word[0], word[1], word[2], word[3]);
+    }
+  }
 }
 
 // Slot-major answers -> polynomial-major: out[p][s] = sm[s * p_stride + p0 + p].
@@ -271,9 +296,8 @@ hipError_t launch_pack_query_slot(const uint32_t *q_ntt, uint8_t *qatoms, uint32
                                   hipStream_t s) {
   if (2 * col_slot + 1 >= n_cb * kCB) return hipErrorInvalidValue;
   const uint32_t n_ib = r_pad(R) / kIB;
-  const size_t total = (size_t)K * N * n_ib * 16;
-  k_pack_query_slot<<<(unsigned)((total + 255) / 256), 256, 0, s>>>(q_ntt, qatoms, col_slot, n_cb,
-                                                                   R, N, K, n_ib);
+  const dim3 grid(N / 32, (n_ib + kPqIB - 1) / kPqIB, K);
+  k_pack_query_slot<<<grid, 256, 0, s>>>(q_ntt, qatoms, col_slot, n_cb, R, N, K, n_ib);
   return hipGetLastError();
 }
 

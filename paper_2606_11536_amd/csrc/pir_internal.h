@@ -125,7 +125,8 @@ hipError_t launch_read_db(const DbDesc &db, uint32_t i0, uint32_t ni, uint32_t j
 hipError_t launch_pack_query(const uint32_t *q_ntt, uint8_t *qatoms, uint32_t B, uint32_t R,
                              uint32_t N, uint32_t K, hipStream_t s);
 // Pack one NTT-form query [R][2][K][N] into columns 2*col_slot, 2*col_slot+1
-// of query atoms with n_cb column blocks, touching no other column's bytes.
+// of column-block-major query atoms [K][N][n_cb][n_ib] (ScanJob::cb_major),
+// touching no other column's bytes.
 hipError_t launch_pack_query_slot(const uint32_t *q_ntt, uint8_t *qatoms, uint32_t col_slot,
                                   uint32_t n_cb, uint32_t R, uint32_t N, uint32_t K,
                                   hipStream_t s);
@@ -145,6 +146,9 @@ struct ScanJob {
   uint32_t slot0, n_slots;
   uint32_t cb_stride;      // column blocks per (k, t, ib) in qatoms; 0 = ceil(2B/8)
   uint32_t p_stride;       // batched kernel: row pitch of out in words; 0 = 2 B C
+  // batched kernel: qatoms ordered [K][N][cb_stride][n_ib] (1) instead of
+  // [K][N][n_ib][cb_stride] (0), so that one column block's atoms are contiguous
+  uint32_t cb_major;
 };
 
 // A scan kernel variant.  kind 0: batch-1 streaming kernel (jbw row blocks per

@@ -388,9 +388,10 @@ constexpr uint32_t kKCB = 4;  // contraction steps per staged query chunk
 
 struct MfJob {
   DbDesc db;
-  const uint8_t *qatoms;  // query atoms [K][N][n_ib][cb_stride]
+  const uint8_t *qatoms;  // query atoms [K][N][n_ib][cb_stride] or [K][N][cb_stride][n_ib]
   uint32_t *out;          // answers, slot-major: [K N][p_stride]
   uint32_t B, n_cb, cb_stride, p_stride;
+  uint32_t q_ibs, q_cbs;  // atoms between consecutive ib, and between consecutive cb
   uint32_t slot0, n_jg, n_cbt;  // work item = (slot, row group, column tile)
   uint32_t n_items, n_blocks;   // items; blocks (block L takes items L, L + n_blocks, ...)
   uint32_t first;               // first logical block of this job
@@ -499,7 +500,7 @@ __global__ __launch_bounds__(256, OCC) void k_scan_mfma(const MfArgs args) {
   const DbDesc &db = a.db;
   const uint32_t tid = threadIdx.x, lane = tid & 63;
   const uint32_t wave = __builtin_amdgcn_readfirstlane(tid >> 6);
-  const uint32_t n_ib = db.n_ib, cbs = a.cb_stride;
+  const uint32_t n_ib = db.n_ib, q_ibs = a.q_ibs, q_cbs = a.q_cbs;
   // Steps per item: n_ib rounded up to the ring depth, and at least as many
   // chunks as the staging looks ahead (two, three with LDS DMA), so that it
   // never reaches past the next item.  Extra steps meet zero query atoms; their
@@ -546,7 +547,7 @@ __global__ __launch_bounds__(256, OCC) void k_scan_mfma(const MfArgs args) {
       const bool ok = live && (kAtoms % 4 == 0 || ai < kAtoms) && ks < n_ib && c < ncb;
       // offsets are below 2^26; setting bit 31 puts a dead load past the
       // resource's end (zeros) without a branch
-      const uint32_t off = (((ks * cbs + cb0 + c) * 64 + lane) * 16) | ((uint32_t)!ok << 31);
+      const uint32_t off = (((ks * q_ibs + (cb0 + c) * q_cbs) * 64 + lane) * 16) | ((uint32_t)!ok << 31);
       st[r] = __builtin_bit_cast(v4i, __builtin_amdgcn_raw_buffer_load_b128(rs, off, 0, 0));
     }
   };
@@ -570,7 +571,7 @@ __global__ __launch_bounds__(256, OCC) void k_scan_mfma(const MfArgs args) {
       const uint32_t ai = wave + 4 * r;
       const uint32_t kk = ai / CBW, c = ai % CBW, ks = ln * kKCB + kk;
       const bool ok = live && ks < n_ib && c < ncb;
-      const uint32_t off = (((ks * cbs + cb0 + c) * 64 + lane) * 16) | ((uint32_t)!ok << 31);
+      const uint32_t off = (((ks * q_ibs + (cb0 + c) * q_cbs) * 64 + lane) * 16) | ((uint32_t)!ok << 31);
       const uint32_t lds = (uint32_t)(size_t)(sq + (bi * kAtoms + ai) * 64);
       lds_dma_b128(rs, off, __builtin_amdgcn_readfirstlane(lds));
     }
@@ -857,6 +858,8 @@ hipError_t run_mfma(const ScanJob *jobs, size_t n, hipStream_t s, hipEvent_t e0,
     m.B = job.B;
     m.n_cb = (2 * job.B + kCB - 1) / kCB;
     m.cb_stride = job.cb_stride ? job.cb_stride : m.n_cb;
+    m.q_ibs = job.cb_major ? 1 : m.cb_stride;
+    m.q_cbs = job.cb_major ? job.db.n_ib : 1;
     m.p_stride = job.p_stride ? job.p_stride : 2 * job.B * job.db.C;
     m.n_jg = (job.db.n_jb + 4 * JBW - 1) / (4 * JBW);
     m.n_cbt = (m.n_cb + CBW - 1) / CBW;

@@ -27,7 +27,7 @@ struct pir_server {
   DbDesc d{};
   uint32_t max_batch = 0, n_cb = 0;
   CircularScan sched{1, 1, 1};
-  uint8_t *qatoms = nullptr;
+  uint8_t *qatoms = nullptr;    // query atoms [K][N][n_cb][n_ib] (column block major)
   uint32_t *ans = nullptr;      // answer state, slot-major: [K N][2 max_batch C]
   uint32_t *scratch = nullptr;  // NTT-form query of an admission
   size_t qatoms_bytes = 0, ans_bytes = 0, scratch_bytes = 0;
@@ -234,7 +234,7 @@ pir_status pir_server_step(pir_server *s, pir_stream stream, uint32_t *admitted,
   const uint32_t b_eff = sc.b_eff();
   if (b_eff) {
     const uint32_t slot0 = sc.range_begin(sc.chunk()), n = sc.range_end(sc.chunk()) - slot0;
-    ScanJob job{d, s->qatoms, nullptr, s->ans, b_eff, slot0, n, s->n_cb, 2 * s->max_batch * d.C};
+    ScanJob job{d, s->qatoms, nullptr, s->ans, b_eff, slot0, n, s->n_cb, 2 * s->max_batch * d.C, 1};
     HIP_OR_FAIL(ctx, launch_scan(&job, 1, server_scan_cfg(ctx, d, b_eff), st));
   }
   // 3. queries that have now met every range finish; a drain that cannot be
