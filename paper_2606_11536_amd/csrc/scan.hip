@@ -416,7 +416,7 @@ struct MfItem {
   __amdgpu_buffer_rsrc_t qrs;    // the slot's query atoms
 };
 
-template <int JBW, int CBW>
+template <int JBW, int CBW, int NW>
 __device__ __forceinline__ void mf_item(const MfJob &a, uint32_t it, uint32_t wave,
                                         MfItem<JBW> &m) {
   const DbDesc &db = a.db;
@@ -428,7 +428,7 @@ __device__ __forceinline__ void mf_item(const MfJob &a, uint32_t it, uint32_t wa
   m.ncb = min((uint32_t)CBW, a.n_cb - m.cb0);
 #pragma unroll
   for (int w = 0; w < JBW; ++w) {
-    m.jbs[w] = (jg * 4 + wave) * JBW + w;
+    m.jbs[w] = (jg * NW + wave) * JBW + w;
     m.jv[w] = m.jbs[w] < db.n_jb;
     // rows past C read row block 0: valid memory, results discarded
     m.rows[w] = db.atoms +
@@ -441,8 +441,9 @@ __device__ __forceinline__ void mf_item(const MfJob &a, uint32_t it, uint32_t wa
                                             (int)q_bytes, kBufferWord3);
 }
 
-// A block is four waves; wave w owns row blocks (4 jg + w) JBW .. + JBW - 1 and
-// CBW query column blocks of one work item (slot, jg, column tile).  Blocks
+// A block is NW waves (four: one per SIMD; eight: two per SIMD sharing one
+// query chunk); wave w owns row blocks (NW jg + w) JBW .. + JBW - 1 and CBW
+// query column blocks of one work item (slot, jg, column tile).  Blocks
 // are persistent over a strided sequence of items (L, L + n_blocks, ...), so
 // blocks running at the same time work on neighbouring items and share the
 // slot's query atoms in L2.  The contraction of an item runs over S steps
@@ -481,17 +482,18 @@ __device__ __forceinline__ void lds_dma_b128(__amdgpu_buffer_rsrc_t rs, uint32_t
   asm volatile("buffer_load_dwordx4 %0, %1, 0 offen lds" ::"v"(off), "s"(rs), "{m0}"(lds) : "memory");
 }
 
-template <int JBW, int CBW, int D, int OCC, bool NTR>
-__global__ __launch_bounds__(256, OCC) void k_scan_mfma(const MfArgs args) {
+template <int JBW, int CBW, int D, int OCC, int NW, bool NTR>
+__global__ __launch_bounds__(64 * NW, OCC) void k_scan_mfma(const MfArgs args) {
   static_assert(D % kKCB == 0 && kKCB >= 2, "ring depth must be a multiple of the query chunk");
   constexpr uint32_t kAtoms = kKCB * CBW;      // query atoms per chunk
   constexpr uint32_t kBuf = kAtoms * 64;       // uint4 per LDS buffer
-  constexpr uint32_t kPer = (kAtoms + 3) / 4;  // chunk atoms per wave
+  constexpr uint32_t kPer = (kAtoms + NW - 1) / NW;  // chunk atoms per wave
+  constexpr int kWps = NW / 4 * OCC;                  // waves per SIMD
   constexpr int kM = JBW * CBW;                // MFMAs per step
   // Query chunks go straight to LDS through three buffers when they fit
   // (160 KiB of LDS per CU), else through staging registers and two buffers.
   constexpr bool kDma = 3 * kBuf * 16 * OCC <= 160 * 1024;
-  static_assert(kAtoms % 4 == 0, "every wave stages the same number of atoms");
+  static_assert(kAtoms % NW == 0, "every wave stages the same number of atoms");
   __shared__ uint4 sq[(kDma ? 3 : 2) * kBuf];
   const uint32_t Lg = xcd_logical(blockIdx.x, gridDim.x);
   if (Lg >= args.total) return;
@@ -512,9 +514,9 @@ __global__ __launch_bounds__(256, OCC) void k_scan_mfma(const MfArgs args) {
 
   uint32_t it = L;
   MfItem<JBW> cur, nxt;
-  mf_item<JBW, CBW>(a, it, wave, cur);
+  mf_item<JBW, CBW, NW>(a, it, wave, cur);
   bool has_next = it + a.n_blocks < a.n_items;
-  if (has_next) mf_item<JBW, CBW>(a, it + a.n_blocks, wave, nxt);
+  if (has_next) mf_item<JBW, CBW, NW>(a, it + a.n_blocks, wave, nxt);
   else nxt = cur;
 
   // atom of step ks (< S + D) of row block w: this item, else the next item's
@@ -532,7 +534,7 @@ __global__ __launch_bounds__(256, OCC) void k_scan_mfma(const MfArgs args) {
     }
   };
   // query atoms of chunk n (< nc + 2) counted from this item's first: atom
-  // (kk, c) of a chunk goes to wave (kk CBW + c) mod 4; zero past n_ib, past
+  // (kk, c) of a chunk goes to wave (kk CBW + c) mod NW; zero past n_ib, past
   // the batch's column blocks and past the last item
   auto stage_load = [&](uint32_t n, v4i (&st)[kPer]) {
     const bool mine = n < nc;
@@ -542,9 +544,9 @@ __global__ __launch_bounds__(256, OCC) void k_scan_mfma(const MfArgs args) {
     const __amdgpu_buffer_rsrc_t rs = mine ? cur.qrs : nxt.qrs;
 #pragma unroll
     for (uint32_t r = 0; r < kPer; ++r) {
-      const uint32_t ai = wave + 4 * r;
+      const uint32_t ai = wave + NW * r;
       const uint32_t kk = ai / CBW, c = ai % CBW, ks = ln * kKCB + kk;
-      const bool ok = live && (kAtoms % 4 == 0 || ai < kAtoms) && ks < n_ib && c < ncb;
+      const bool ok = live && (kAtoms % NW == 0 || ai < kAtoms) && ks < n_ib && c < ncb;
       // offsets are below 2^26; setting bit 31 puts a dead load past the
       // resource's end (zeros) without a branch
       const uint32_t off = (((ks * q_ibs + (cb0 + c) * q_cbs) * 64 + lane) * 16) | ((uint32_t)!ok << 31);
@@ -554,8 +556,8 @@ __global__ __launch_bounds__(256, OCC) void k_scan_mfma(const MfArgs args) {
   auto stage_store = [&](uint4 *buf, const v4i (&st)[kPer]) {
 #pragma unroll
     for (uint32_t r = 0; r < kPer; ++r) {
-      const uint32_t ai = wave + 4 * r;
-      if (kAtoms % 4 == 0 || ai < kAtoms)
+      const uint32_t ai = wave + NW * r;
+      if (kAtoms % NW == 0 || ai < kAtoms)
         buf[ai * 64 + lane] = make_uint4(st[r].x, st[r].y, st[r].z, st[r].w);
     }
   };
@@ -568,7 +570,7 @@ __global__ __launch_bounds__(256, OCC) void k_scan_mfma(const MfArgs args) {
     const __amdgpu_buffer_rsrc_t rs = mine ? cur.qrs : nxt.qrs;
 #pragma unroll
     for (uint32_t r = 0; r < kPer; ++r) {
-      const uint32_t ai = wave + 4 * r;
+      const uint32_t ai = wave + NW * r;
       const uint32_t kk = ai / CBW, c = ai % CBW, ks = ln * kKCB + kk;
       const bool ok = live && ks < n_ib && c < ncb;
       const uint32_t off = (((ks * q_ibs + (cb0 + c) * q_cbs) * 64 + lane) * 16) | ((uint32_t)!ok << 31);
@@ -584,7 +586,7 @@ __global__ __launch_bounds__(256, OCC) void k_scan_mfma(const MfArgs args) {
     }
   };
 
-  constexpr bool kPf = OCC == 1 || JBW * D * 4 + CBW * 8 <= 64;
+  constexpr bool kPf = kWps == 1 || JBW * D * 4 + CBW * 8 <= 64;
   // LDS DMA: chunk n + 3 is requested right after the barrier that publishes
   // chunk n + 1, into the buffer chunk n used, and waited for at the barrier
   // that publishes it.  By then this wave has issued, after it, the ring loads
@@ -623,7 +625,7 @@ __global__ __launch_bounds__(256, OCC) void k_scan_mfma(const MfArgs args) {
   constexpr int kPub = kPf ? (int)kKCB - 2 : (int)kKCB - 1;
   // MFMAs issued ahead of a publishing barrier (one wave per SIMD only: their
   // pin keeps the accumulators in AGPRs, which two waves per SIMD cannot afford)
-  constexpr int kPre = OCC > 1 ? 0 : kM < 2 ? kM : 2;
+  constexpr int kPre = kWps > 1 ? 0 : kM < 2 ? kM : 2;
   v4i bcur[CBW], bnext[CBW];
   if (kPf) b_read(sq, bcur);
 
@@ -771,7 +773,7 @@ __global__ __launch_bounds__(256, OCC) void k_scan_mfma(const MfArgs args) {
     it += a.n_blocks;
     cur = nxt;
     has_next = it + a.n_blocks < a.n_items;
-    if (has_next) mf_item<JBW, CBW>(a, it + a.n_blocks, wave, nxt);
+    if (has_next) mf_item<JBW, CBW, NW>(a, it + a.n_blocks, wave, nxt);
   }
   // LDS DMA requests past the last chunk are still in flight: the wave may
   // not end before they have written this workgroup's LDS
@@ -839,7 +841,7 @@ hipError_t run_b1r(const ScanJob *jobs, size_t n, hipStream_t s, hipEvent_t e0, 
 // (four per CU on 256 CUs) when it has that many items.
 constexpr uint32_t kItemsPerBlock = 16, kMinBlocks = 1024;
 
-template <int JBW, int CBW, int D, int OCC>
+template <int JBW, int CBW, int D, int OCC, int NW>
 hipError_t run_mfma(const ScanJob *jobs, size_t n, hipStream_t s, hipEvent_t e0, hipEvent_t e1) {
   constexpr uint32_t kAtomsChunk = kKCB * CBW;
   constexpr bool kDma = 3 * kAtomsChunk * 64 * 16 * OCC <= 160 * 1024;  // as in the kernel
@@ -861,7 +863,7 @@ hipError_t run_mfma(const ScanJob *jobs, size_t n, hipStream_t s, hipEvent_t e0,
     m.q_ibs = job.cb_major ? 1 : m.cb_stride;
     m.q_cbs = job.cb_major ? job.db.n_ib : 1;
     m.p_stride = job.p_stride ? job.p_stride : 2 * job.B * job.db.C;
-    m.n_jg = (job.db.n_jb + 4 * JBW - 1) / (4 * JBW);
+    m.n_jg = (job.db.n_jb + NW * JBW - 1) / (NW * JBW);
     m.n_cbt = (m.n_cb + CBW - 1) / CBW;
     m.slot0 = job.slot0;
     m.n_items = job.n_slots * m.n_jg * m.n_cbt;
@@ -878,11 +880,11 @@ hipError_t run_mfma(const ScanJob *jobs, size_t n, hipStream_t s, hipEvent_t e0,
   bool one_tile = true;
   for (size_t i = 0; i < n; ++i) one_tile = one_tile && a.jobs[i].n_cbt == 1;
   if (one_tile)
-    hipExtLaunchKernelGGL(k_scan_mfma<JBW, CBW, D, OCC, true>, dim3(round8(total)), dim3(256), 0, s,
-                          e0, e1, 0, a);
+    hipExtLaunchKernelGGL(k_scan_mfma<JBW, CBW, D, OCC, NW, true>, dim3(round8(total)),
+                          dim3(64 * NW), 0, s, e0, e1, 0, a);
   else
-    hipExtLaunchKernelGGL(k_scan_mfma<JBW, CBW, D, OCC, false>, dim3(round8(total)), dim3(256), 0,
-                          s, e0, e1, 0, a);
+    hipExtLaunchKernelGGL(k_scan_mfma<JBW, CBW, D, OCC, NW, false>, dim3(round8(total)),
+                          dim3(64 * NW), 0, s, e0, e1, 0, a);
   return hipGetLastError();
 }
 
@@ -894,9 +896,12 @@ struct Variant {
 };
 
 // ScanCfg for kind 0: jbw, unr = k-blocks in flight, nt = nontemporal | ring << 1.
-// ScanCfg for kind 1: jbw, unr = ring depth D, nt = log2(CBW) | (OCC - 1) << 4.
-#define MF(J, C, D, O) \
-  {{1, J, D, (C == 8 ? 3 : C == 4 ? 2 : C == 2 ? 1 : 0) | ((O - 1) << 4)}, run_mfma<J, C, D, O>}
+// ScanCfg for kind 1: jbw, unr = ring depth D, nt = log2(CBW) | (OCC - 1) << 4
+// | (NW == 8) << 5.
+#define MFW(J, C, D, O, W)                                                                 \
+  {{1, J, D, (C == 8 ? 3 : C == 4 ? 2 : C == 2 ? 1 : 0) | ((O - 1) << 4) | ((W == 8) << 5)}, \
+   run_mfma<J, C, D, O, W>}
+#define MF(J, C, D, O) MFW(J, C, D, O, 4)
 const Variant kVariants[] = {
     // batch-1 streaming, grouped loads and ring
     {{0, 8, 4, 1}, run_b1<8, 4, true>},  {{0, 4, 8, 1}, run_b1<4, 8, true>},
@@ -908,8 +913,11 @@ const Variant kVariants[] = {
     MF(1, 2, 8, 1), MF(2, 2, 8, 1), MF(4, 2, 8, 1), MF(2, 2, 8, 2),
     MF(1, 4, 8, 1), MF(2, 4, 8, 1), MF(2, 4, 4, 2), MF(2, 4, 8, 2), MF(4, 4, 8, 1), MF(4, 4, 4, 1),
     MF(1, 8, 8, 1), MF(2, 8, 8, 1), MF(2, 8, 4, 1), MF(1, 8, 4, 2), MF(1, 8, 8, 2),
+    // eight waves per block, two per SIMD, sharing one query chunk
+    MFW(1, 8, 8, 1, 8), MFW(1, 8, 4, 1, 8), MFW(2, 4, 8, 1, 8), MFW(2, 4, 4, 1, 8),
 };
 #undef MF
+#undef MFW
 
 // Column blocks per wave worth trying for a batch of B queries.
 uint32_t cbw_for(uint32_t B) {
