@@ -913,7 +913,8 @@ const Variant kVariants[] = {
     MF(1, 2, 8, 1), MF(2, 2, 8, 1), MF(4, 2, 8, 1), MF(2, 2, 8, 2),
     MF(1, 4, 8, 1), MF(2, 4, 8, 1), MF(2, 4, 4, 2), MF(2, 4, 8, 2), MF(4, 4, 8, 1), MF(4, 4, 4, 1),
     MF(1, 8, 8, 1), MF(2, 8, 8, 1), MF(2, 8, 4, 1), MF(1, 8, 4, 2), MF(1, 8, 8, 2),
-    // eight waves per block, two per SIMD, sharing one query chunk
+    // eight waves per block, two per SIMD, sharing one query chunk (sixteen
+    // waves of (1,4) tiles measured 3-5 % slower than eight of (2,4))
     MFW(1, 8, 8, 1, 8), MFW(1, 8, 4, 1, 8), MFW(2, 4, 8, 1, 8), MFW(2, 4, 4, 1, 8),
 };
 #undef MF
@@ -938,17 +939,18 @@ std::vector<ScanCfg> scan_candidates(uint32_t B) {
   return out;
 }
 
+// From eight column blocks up, the eight-wave (2,4) tile with an 8-deep ring
+// (fastest at B = 32 and 128); below, the four-wave (2, cbw) tile.
 ScanCfg scan_default_mfma(uint32_t B) {
   const uint32_t cbw = cbw_for(B);
-  const uint8_t lg = cbw == 8 ? 3 : cbw == 4 ? 2 : cbw == 2 ? 1 : 0;
+  if (cbw == 8) return ScanCfg{1, 2, 8, 2 | (1 << 5)};
+  const uint8_t lg = cbw == 4 ? 2 : cbw == 2 ? 1 : 0;
   return ScanCfg{1, 2, 8, lg};
 }
 
 ScanCfg scan_default(uint32_t B) {
   if (B == 1) return ScanCfg{0, 4, 4, 3};
-  const uint32_t cbw = cbw_for(B);
-  const uint8_t lg = cbw == 8 ? 3 : cbw == 4 ? 2 : cbw == 2 ? 1 : 0;
-  return ScanCfg{1, 2, 8, lg};
+  return scan_default_mfma(B);
 }
 
 const char *scan_kernel_name(const ScanCfg &cfg, const DbDesc &d) {
