@@ -47,10 +47,15 @@ constexpr uint32_t kB1Chunk = 64;  // query ibs split into LDS per chunk (16 KiB
 // Instruction-class masks of the scheduling-group builtin.
 constexpr int kSgMfma = 0x008, kSgVmemRead = 0x020, kSgDsRead = 0x100, kSgDsWrite = 0x200;
 
-// Scan launches take a table of up to kMaxFused jobs; the logical block
-// index space is the concatenation of the jobs' spaces (job j owns logical
-// blocks [first, first + blocks)).  A block finds its job by a uniform
-// search of the table in the kernel-argument segment.
+// Scan launches take a table of up to kMaxFused jobs.  The grid is the
+// concatenation of the jobs' blocks, each job's count rounded up to a
+// multiple of 8 (job j owns grid blocks [first, first + round8(n_blocks))),
+// so every job is spread evenly over the 8 XCDs; inside a job the blocks of
+// one XCD take a contiguous run of the job's logical indices.  (One XCD-
+// contiguous mapping over the whole concatenation would hand whole XCDs to
+// one job, and jobs whose blocks cost different amounts would leave XCDs
+// idle.)  A block finds its job by a uniform search of the table in the
+// kernel-argument segment.
 constexpr int kMaxFused = 8;
 
 struct B1Job {
@@ -59,7 +64,8 @@ struct B1Job {
   uint32_t *out;      // answer [1][C][2][K][N]
   uint32_t slot0, n_slots;  // slots scanned: [slot0, slot0 + n_slots)
   uint32_t jpb;       // jbs per block
-  uint32_t first;     // first logical block of this job
+  uint32_t n_blocks;  // blocks of this job
+  uint32_t first;     // first grid block of this job (a multiple of 8)
 };
 
 struct B1Args {
@@ -68,12 +74,19 @@ struct B1Args {
 };
 
 template <typename Args>
-__device__ __forceinline__ uint32_t find_job(const Args &a, uint32_t L) {
+__device__ __forceinline__ uint32_t find_job(const Args &a, uint32_t bid) {
   uint32_t jid = 0;
 #pragma unroll
   for (int j = 1; j < kMaxFused; ++j)
-    if ((uint32_t)j < a.n_jobs && L >= a.jobs[j].first) jid = j;
+    if ((uint32_t)j < a.n_jobs && bid >= a.jobs[j].first) jid = j;
   return jid;
+}
+
+// The logical index of grid block `bid` inside its job (see above); at or
+// beyond the job's n_blocks the block is idle.
+template <typename Job>
+__device__ __forceinline__ uint32_t job_logical(const Job &a, uint32_t bid) {
+  return xcd_logical(bid - a.first, (a.n_blocks + 7u) & ~7u);
 }
 
 // Reduce the lane's partial sum s over the 4 lanes b = 0..3 (lane bits 0,1)
@@ -199,10 +212,10 @@ __device__ __forceinline__ void b1_epilogue(const v4i (&acc)[2], uint32_t jb, ui
 template <int JBW, int UNR, bool NT>
 __global__ __launch_bounds__(256) void k_scan_b1(const B1Args args) {
   __shared__ uint32_t sq[kB1Chunk * 64];
-  const uint32_t Lg = xcd_logical(blockIdx.x, gridDim.x);
-  if (Lg >= args.total) return;
-  const B1Job &a = args.jobs[find_job(args, Lg)];
-  const uint32_t L = Lg - a.first;
+  if (blockIdx.x >= args.total) return;
+  const B1Job &a = args.jobs[find_job(args, blockIdx.x)];
+  const uint32_t L = job_logical(a, blockIdx.x);
+  if (L >= a.n_blocks) return;
   const DbDesc &db = a.db;
   const uint32_t slot = a.slot0 + L % a.n_slots, jchunk = L / a.n_slots;
   const uint32_t k = slot >> db.log2n, t = slot & (db.N - 1);
@@ -282,10 +295,10 @@ __global__ __launch_bounds__(256) void k_scan_b1(const B1Args args) {
 template <int JBW, int D, bool NT>
 __global__ __launch_bounds__(256) void k_scan_b1r(const B1Args args) {
   __shared__ uint32_t sq[kB1Chunk * 64];
-  const uint32_t Lg = xcd_logical(blockIdx.x, gridDim.x);
-  if (Lg >= args.total) return;
-  const B1Job &a = args.jobs[find_job(args, Lg)];
-  const uint32_t L = Lg - a.first;
+  if (blockIdx.x >= args.total) return;
+  const B1Job &a = args.jobs[find_job(args, blockIdx.x)];
+  const uint32_t L = job_logical(a, blockIdx.x);
+  if (L >= a.n_blocks) return;
   const DbDesc &db = a.db;
   const uint32_t slot = a.slot0 + L % a.n_slots, jchunk = L / a.n_slots;
   const uint32_t k = slot >> db.log2n, t = slot & (db.N - 1);
@@ -495,10 +508,10 @@ __global__ __launch_bounds__(64 * NW, OCC) void k_scan_mfma(const MfArgs args) {
   constexpr bool kDma = 3 * kBuf * 16 * OCC <= 160 * 1024;
   static_assert(kAtoms % NW == 0, "every wave stages the same number of atoms");
   __shared__ uint4 sq[(kDma ? 3 : 2) * kBuf];
-  const uint32_t Lg = xcd_logical(blockIdx.x, gridDim.x);
-  if (Lg >= args.total) return;
-  const MfJob &a = args.jobs[find_job(args, Lg)];
-  const uint32_t L = Lg - a.first;
+  if (blockIdx.x >= args.total) return;
+  const MfJob &a = args.jobs[find_job(args, blockIdx.x)];
+  const uint32_t L = job_logical(a, blockIdx.x);
+  if (L >= a.n_blocks) return;
   const DbDesc &db = a.db;
   const uint32_t tid = threadIdx.x, lane = tid & 63;
   const uint32_t wave = __builtin_amdgcn_readfirstlane(tid >> 6);
@@ -797,13 +810,14 @@ hipError_t run_b1(const ScanJob *jobs, size_t n, hipStream_t s, hipEvent_t e0, h
     b.slot0 = job.slot0;
     b.n_slots = job.n_slots;
     b.jpb = 4 * JBW;
+    b.n_blocks = b.n_slots * ((job.db.n_jb + b.jpb - 1) / b.jpb);
     b.first = total;
-    total += b.n_slots * ((job.db.n_jb + b.jpb - 1) / b.jpb);
+    total += round8(b.n_blocks);
   }
   a.n_jobs = (uint32_t)n;
   a.total = total;
   if (total == 0) return hipSuccess;
-  hipExtLaunchKernelGGL(k_scan_b1<JBW, UNR, NT>, dim3(round8(total)), dim3(256), 0, s, e0, e1, 0, a);
+  hipExtLaunchKernelGGL(k_scan_b1<JBW, UNR, NT>, dim3(total), dim3(256), 0, s, e0, e1, 0, a);
   return hipGetLastError();
 }
 
@@ -826,13 +840,14 @@ hipError_t run_b1r(const ScanJob *jobs, size_t n, hipStream_t s, hipEvent_t e0, 
     b.slot0 = job.slot0;
     b.n_slots = job.n_slots;
     b.jpb = 4 * JBW;
+    b.n_blocks = b.n_slots * ((job.db.n_jb + b.jpb - 1) / b.jpb);
     b.first = total;
-    total += b.n_slots * ((job.db.n_jb + b.jpb - 1) / b.jpb);
+    total += round8(b.n_blocks);
   }
   a.n_jobs = (uint32_t)n;
   a.total = total;
   if (total == 0) return hipSuccess;
-  hipExtLaunchKernelGGL(k_scan_b1r<JBW, D, NT>, dim3(round8(total)), dim3(256), 0, s, e0, e1, 0, a);
+  hipExtLaunchKernelGGL(k_scan_b1r<JBW, D, NT>, dim3(total), dim3(256), 0, s, e0, e1, 0, a);
   return hipGetLastError();
 }
 
@@ -872,7 +887,7 @@ hipError_t run_mfma(const ScanJob *jobs, size_t n, hipStream_t s, hipEvent_t e0,
     m.n_blocks = std::max(std::min(m.n_items, kMinBlocks * OCC),
                           (m.n_items + kItemsPerBlock - 1) / kItemsPerBlock);
     m.first = total;
-    total += m.n_blocks;
+    total += round8(m.n_blocks);
   }
   a.n_jobs = (uint32_t)n;
   a.total = total;
@@ -880,10 +895,10 @@ hipError_t run_mfma(const ScanJob *jobs, size_t n, hipStream_t s, hipEvent_t e0,
   bool one_tile = true;
   for (size_t i = 0; i < n; ++i) one_tile = one_tile && a.jobs[i].n_cbt == 1;
   if (one_tile)
-    hipExtLaunchKernelGGL(k_scan_mfma<JBW, CBW, D, OCC, NW, true>, dim3(round8(total)),
+    hipExtLaunchKernelGGL(k_scan_mfma<JBW, CBW, D, OCC, NW, true>, dim3(total),
                           dim3(64 * NW), 0, s, e0, e1, 0, a);
   else
-    hipExtLaunchKernelGGL(k_scan_mfma<JBW, CBW, D, OCC, NW, false>, dim3(round8(total)),
+    hipExtLaunchKernelGGL(k_scan_mfma<JBW, CBW, D, OCC, NW, false>, dim3(total),
                           dim3(64 * NW), 0, s, e0, e1, 0, a);
   return hipGetLastError();
 }
