@@ -54,8 +54,8 @@ __device__ __forceinline__ uint32_t map_src(uint32_t pos, const PolyMap &m, uint
 __device__ __forceinline__ int64_t crt_centred(uint32_t x0, uint32_t x1, const GadgetArgs &g) {
   uint64_t x = x0;
   if (g.K == 2) {
-    const double q1 = (double)g.q1, inv_q1 = 1.0 / q1;
-    const double r = mulmod_exact((double)x1 - (double)x0, g.c, q1, inv_q1);  // |r| < 0.51 q1
+    const double q1 = (double)g.q1;
+    const double r = mulmod_exact((double)x1 - (double)x0, g.c, q1, g.inv_q1);  // |r| < 0.51 q1
     const uint32_t y = (uint32_t)(int)(r < 0.0 ? r + q1 : r);
     x += (uint64_t)g.q0 * y;                                                  // < Q
   }
@@ -139,6 +139,8 @@ __global__ __launch_bounds__(kThreads) void k_gadget_mac(const uint32_t *__restr
   const uint32_t *key = keys + (p / ppk) * key_stride + kt;
   const uint32_t *d = dig + p * rows * KN + kt;
   double s0 = 0.0, s1 = 0.0;  // |s| < rows * 0.51 q < 2^34: exact
+  // unrolled so that several rows' loads are in flight at once
+#pragma unroll 4
   for (uint32_t r = 0; r < rows; ++r) {
     const double dv = (double)d[(size_t)r * KN];
     s0 += mulmod_exact(dv, (double)key[(size_t)(2 * r) * KN], q, inv_q);
