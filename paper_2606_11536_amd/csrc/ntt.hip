@@ -1,10 +1,12 @@
 // Negacyclic NTT / INTT over Z_q[X]/(X^N + 1), q < 2^28, N in {1024, 2048, 4096}
 // (paper: Sec. 2.3; single-kernel transform of Sec. 4.3).
 //
-// One 256-thread workgroup transforms one residue row of N values.  Each
-// thread keeps E = N/256 values in registers and performs log2(E) radix-2
-// stages on them before the block exchanges values through LDS; the
-// log2(N) stages therefore take ceil(log2 N / log2 E) register rounds.
+// One workgroup transforms one residue row of N values: 256 threads for
+// N <= 2048, 512 for N = 4096 (so that a thread holds at most 8 values and
+// stays near 60 VGPRs, eight waves per SIMD).  Each thread keeps E values in
+// registers and performs log2(E) radix-2 stages on them before the block
+// exchanges values through LDS; the log2(N) stages therefore take
+// ceil(log2 N / log2 E) register rounds.
 //
 // Forward: Cooley-Tukey stages with half-sizes N/2, N/4, ..., 1; the stage
 // with half-size h uses twiddle psi^brv(N/(2h) + x/(2h)) for the pair
@@ -30,12 +32,12 @@
 namespace pir {
 namespace {
 
-constexpr int kThreads = 256;
-
 template <int LOGN>
 struct Geo {
   static constexpr int N = 1 << LOGN;
-  static constexpr int LE = LOGN - 8;  // log2 of values per thread
+  static constexpr int LT = LOGN >= 12 ? 9 : 8;  // log2 of threads per row
+  static constexpr int T = 1 << LT;
+  static constexpr int LE = LOGN - LT;  // log2 of values per thread
   static constexpr int E = 1 << LE;
   static constexpr int ROUNDS = (LOGN + LE - 1) / LE;
   static constexpr int REM = LOGN - (ROUNDS - 1) * LE;  // stages in the short round
@@ -71,7 +73,7 @@ __device__ __forceinline__ uint32_t ridx(uint32_t tid, int e) {
   constexpr int LL = G::logL(R, INV);
   const uint32_t g = (uint32_t)e >> S;
   const uint32_t ep = (uint32_t)e & ((1u << S) - 1);
-  const uint32_t gid = tid + g * kThreads;
+  const uint32_t gid = tid + g * G::T;
   const uint32_t x0 = ((gid >> LL) << (LL + S)) + (gid & ((1u << LL) - 1));
   return x0 + (ep << LL);
 }
@@ -152,7 +154,7 @@ __device__ __forceinline__ void transform(double (&x)[Geo<LOGN>::E],
 // (0 | G) term of ring packing, added before the inverse transform (which is
 // linear), so that no separate pass over the answers is needed.
 template <int LOGN, bool INV, bool ADD>
-__global__ __launch_bounds__(kThreads) void k_ntt_rows(const uint32_t *__restrict__ src,
+__global__ __launch_bounds__(Geo<LOGN>::T) void k_ntt_rows(const uint32_t *__restrict__ src,
                                                        uint32_t *__restrict__ dst, uint32_t K,
                                                        const DevPrime *__restrict__ primes,
                                                        const uint32_t *__restrict__ add) {
@@ -185,7 +187,7 @@ __global__ __launch_bounds__(kThreads) void k_ntt_rows(const uint32_t *__restric
 // The unsigned lift: a coefficient v < 2^32 is the integer v, reduced mod q_k
 // by the transform's final reduction.
 template <int LOGN, typename T>
-__global__ __launch_bounds__(kThreads) void k_lift_ntt(const T *__restrict__ raw,
+__global__ __launch_bounds__(Geo<LOGN>::T) void k_lift_ntt(const T *__restrict__ raw,
                                                        uint32_t *__restrict__ out, uint32_t rows,
                                                        uint32_t valid_rows,
                                                        const DevPrime *__restrict__ primes) {
@@ -223,7 +225,7 @@ struct OffsetArgs {
 };
 
 template <int LOGN>
-__global__ __launch_bounds__(kThreads) void k_offset_ntt(const uint32_t *__restrict__ b,
+__global__ __launch_bounds__(Geo<LOGN>::T) void k_offset_ntt(const uint32_t *__restrict__ b,
                                                          uint32_t *__restrict__ out,
                                                          const DevPrime *__restrict__ primes,
                                                          const OffsetArgs a) {
@@ -291,7 +293,7 @@ __device__ __forceinline__ uint32_t mod_switch(uint32_t x0, uint32_t x1, const M
 // With an addend, odd polynomials (component 1 of [..][2] answers) first get
 // polynomial poly / 2 of `add` ([..][K][N]) added, as in k_ntt_rows.
 template <int LOGN, bool TWO, bool ADD>
-__global__ __launch_bounds__(kThreads) void k_intt_switch(const uint32_t *__restrict__ src,
+__global__ __launch_bounds__(Geo<LOGN>::T) void k_intt_switch(const uint32_t *__restrict__ src,
                                                           uint32_t *__restrict__ dst,
                                                           const DevPrime *__restrict__ primes,
                                                           const MsArgs m,
@@ -340,11 +342,11 @@ hipError_t ntt_rows_dispatch(const uint32_t *src, uint32_t *dst, size_t n_rows, 
                              uint32_t log2n, const DevPrime *primes, const uint32_t *add,
                              hipStream_t s) {
   if (n_rows == 0) return hipSuccess;
-  const dim3 grid((unsigned)n_rows), block(kThreads);
+  const dim3 grid((unsigned)n_rows);
   switch (log2n) {
-    case 10: k_ntt_rows<10, INV, ADD><<<grid, block, 0, s>>>(src, dst, K, primes, add); break;
-    case 11: k_ntt_rows<11, INV, ADD><<<grid, block, 0, s>>>(src, dst, K, primes, add); break;
-    case 12: k_ntt_rows<12, INV, ADD><<<grid, block, 0, s>>>(src, dst, K, primes, add); break;
+    case 10: k_ntt_rows<10, INV, ADD><<<grid, Geo<10>::T, 0, s>>>(src, dst, K, primes, add); break;
+    case 11: k_ntt_rows<11, INV, ADD><<<grid, Geo<11>::T, 0, s>>>(src, dst, K, primes, add); break;
+    case 12: k_ntt_rows<12, INV, ADD><<<grid, Geo<12>::T, 0, s>>>(src, dst, K, primes, add); break;
     default: return hipErrorInvalidValue;
   }
   return hipGetLastError();
@@ -353,7 +355,7 @@ hipError_t ntt_rows_dispatch(const uint32_t *src, uint32_t *dst, size_t n_rows, 
 template <int LOGN, bool TWO>
 void intt_switch_launch(const uint32_t *src, uint32_t *dst, size_t n_polys, const DevPrime *primes,
                         const MsArgs &m, const uint32_t *add, hipStream_t s) {
-  const dim3 grid((unsigned)n_polys), block(kThreads);
+  const dim3 grid((unsigned)n_polys), block(Geo<LOGN>::T);
   if (add) k_intt_switch<LOGN, TWO, true><<<grid, block, 0, s>>>(src, dst, primes, m, add);
   else k_intt_switch<LOGN, TWO, false><<<grid, block, 0, s>>>(src, dst, primes, m, nullptr);
 }
@@ -362,11 +364,11 @@ template <typename T>
 hipError_t lift_ntt_dispatch(const T *raw, uint32_t *out, uint32_t S, uint32_t s_valid, uint32_t C,
                              uint32_t K, uint32_t log2n, const DevPrime *primes, hipStream_t s) {
   const uint32_t rows = S * C, valid = s_valid * C;
-  const dim3 grid(rows, K), block(kThreads);
+  const dim3 grid(rows, K);
   switch (log2n) {
-    case 10: k_lift_ntt<10, T><<<grid, block, 0, s>>>(raw, out, rows, valid, primes); break;
-    case 11: k_lift_ntt<11, T><<<grid, block, 0, s>>>(raw, out, rows, valid, primes); break;
-    case 12: k_lift_ntt<12, T><<<grid, block, 0, s>>>(raw, out, rows, valid, primes); break;
+    case 10: k_lift_ntt<10, T><<<grid, Geo<10>::T, 0, s>>>(raw, out, rows, valid, primes); break;
+    case 11: k_lift_ntt<11, T><<<grid, Geo<11>::T, 0, s>>>(raw, out, rows, valid, primes); break;
+    case 12: k_lift_ntt<12, T><<<grid, Geo<12>::T, 0, s>>>(raw, out, rows, valid, primes); break;
     default: return hipErrorInvalidValue;
   }
   return hipGetLastError();
@@ -449,11 +451,11 @@ hipError_t launch_offset_ntt(const uint32_t *b, uint32_t *out, uint32_t B, uint3
   a.Cp = Cp;
   a.K = K;
   for (uint32_t k = 0; k < K; ++k) a.delta[k] = delta[k];
-  const dim3 grid(B * Cp, K), block(kThreads);
+  const dim3 grid(B * Cp, K);
   switch (log2n) {
-    case 10: k_offset_ntt<10><<<grid, block, 0, s>>>(b, out, primes, a); break;
-    case 11: k_offset_ntt<11><<<grid, block, 0, s>>>(b, out, primes, a); break;
-    case 12: k_offset_ntt<12><<<grid, block, 0, s>>>(b, out, primes, a); break;
+    case 10: k_offset_ntt<10><<<grid, Geo<10>::T, 0, s>>>(b, out, primes, a); break;
+    case 11: k_offset_ntt<11><<<grid, Geo<11>::T, 0, s>>>(b, out, primes, a); break;
+    case 12: k_offset_ntt<12><<<grid, Geo<12>::T, 0, s>>>(b, out, primes, a); break;
     default: return hipErrorInvalidValue;
   }
   return hipGetLastError();
